@@ -1,0 +1,162 @@
+"""Throughput of the fused FP32 hybrid-LBM step on one MI355X.
+
+Workload: decaying compressible turbulence on an 8192 x 8192 periodic grid
+(seeded random-phase solenoidal velocity, E(k) ~ k^4 exp(-2 (k/8)^2),
+turbulent Mach 0.5, rho = 1, theta = 240/1183), nu = 1e-3, sigma = 0, FP32
+storage.  One step = one launch of the fused step kernel over the whole grid
+(collision, correction term, streaming and entropy update).
+
+Prints ONE JSON line: MLUPS (million lattice updates per second), the HBM
+roofline of the step kernel, and the FP64 CPU oracle timed on a bounded
+sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("HLBM MLUPS & % HBM roofline @8192² FP32; learned-vs-plain time at equal L2 "
+          "error")
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
+BYTES_PER_NODE = 80            # read 9 populations + s, write 9 + s, FP32
+KERNEL_SRC = os.path.join(ROOT, "paper_2002_03644_amd", "csrc", "hlbm_device.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_f32_turbulence8192_traffic.json")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(nodes: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_hash() or t.get("nodes") != nodes:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(n_sample=1024, steps=12):
+    """The FP64 oracle on an n_sample^2 periodic window of the same
+    turbulence recipe, timed on the host cores (steady-state steps only)."""
+    import numpy as np
+
+    import hlbm_inputs as hi
+    import oracle
+    r, u, v, t = hi.turbulence(n_sample, 0.5, hi.THETA_PAPER, seed=0)
+    S = oracle.OracleSolver(oracle.OracleParams(n_sample, n_sample, mu=1e-3, sigma=0.0),
+                            r, u, v, theta=t)
+    S.step(1)
+    t0 = time.perf_counter()
+    S.step(steps)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(n_sample * n_sample * steps / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": cores, "kind": "oracle",
+            "sample": f"{n_sample}x{n_sample} periodic window of the same turbulence recipe, "
+                      f"{steps} steps after 1 warm-up step, FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--tile-w", type=int, default=0)
+    ap.add_argument("--tile-h", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 2 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "path is a design note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import hlbm_inputs as hi
+    from paper_2002_03644_amd import Params, Solver
+
+    n = args.n
+    print(f"[bench] generating {n}x{n} turbulence", file=sys.stderr, flush=True)
+    r, u, v, t = hi.turbulence(n, 0.5, hi.THETA_PAPER, seed=0)
+    params = Params(n, n, dtype="f32", mu=1e-3, sigma=0.0, tile_w=args.tile_w,
+                    tile_h=args.tile_h)
+    dev = torch.device("cuda:0")
+    fields = [torch.from_numpy(a.astype(np.float32)).to(dev) for a in (r, u, v, t)]
+    del r, u, v, t
+    S = Solver(params, *fields[:3], theta=fields[3], device=dev)
+    del fields
+    torch.cuda.synchronize()
+    print("[bench] warmup", file=sys.stderr, flush=True)
+    S.step(args.warmup)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e0.record(stream)
+    S.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = e0.elapsed_time(e1)
+    ms_per_step = ms_total / args.steps
+    nodes = n * n
+    mlups = nodes * args.steps / (ms_total / 1e3) / 1e6
+    code, max_cfl = S.status()
+    print(f"[bench] {ms_per_step:.4f} ms/step, {mlups:.0f} MLUPS, wall {wall:.2f} s, "
+          f"status {code}, max CFL {max_cfl:.3f}", file=sys.stderr, flush=True)
+
+    achieved = BYTES_PER_NODE * nodes / (ms_per_step / 1e3) / 1e9
+    traffic = measured_traffic(nodes)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic}
+
+    if args.copy_calibration:
+        a = torch.empty(2 ** 31, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    del S
+    torch.cuda.empty_cache()
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
+
+    out = {"metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"decaying compressible turbulence {n}x{n} periodic, "
+                                  "Ma_t 0.5, nu 1e-3, sigma 0, FP32 storage",
+                      "nx": n, "ny": n, "global_batch": 1, "parallelism": "none",
+                      "tile_w": params.tile_w or "auto", "tile_h": params.tile_h or "auto",
+                      "status_after": int(code)},
+           "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

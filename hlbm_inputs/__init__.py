@@ -193,9 +193,12 @@ def rankine_hugoniot(mach, gamma=1.4):
 
 
 def normal_shock(nx, ny, mach=2.0, theta1=0.1, gamma=1.4, rho1=1.0, x_split=None,
-                 perturb=1e-3, seed=0):
-    """Stationary normal shock from Rankine-Hugoniot states; upstream velocity
-    gets a seeded perturbation perturb * u1 * N(0, 1) on both components."""
+                 perturb=1e-3, seed=0, transverse=False):
+    """Stationary normal shock from Rankine-Hugoniot states; the upstream
+    velocity gets a seeded perturbation perturb * u1 * N(0, 1).  By default
+    the perturbation varies along x only (one draw per column, u_x only), so
+    the flow stays quasi-one-dimensional; ``transverse=True`` draws it per
+    node on both components (grid-scale 2-D noise)."""
     if x_split is None:
         x_split = nx // 2
     r, ur, pr, tr, _ = rankine_hugoniot(mach, gamma)
@@ -209,10 +212,13 @@ def normal_shock(nx, ny, mach=2.0, theta1=0.1, gamma=1.4, rho1=1.0, x_split=None
     uy = np.zeros_like(ux)
     if perturb:
         rng = np.random.default_rng(seed)
-        nxp = rng.standard_normal((ny, nx))
-        nyp = rng.standard_normal((ny, nx))
+        if transverse:
+            nxp = rng.standard_normal((ny, nx))
+            nyp = rng.standard_normal((ny, nx))
+            uy = uy + np.where(up, perturb * u1 * nyp, 0.0)
+        else:
+            nxp = np.repeat(rng.standard_normal((1, nx)), ny, axis=0)
         ux = ux + np.where(up, perturb * u1 * nxp, 0.0)
-        uy = uy + np.where(up, perturb * u1 * nyp, 0.0)
     return rho, ux, uy, theta
 
 

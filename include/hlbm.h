@@ -1,0 +1,164 @@
+/*
+ * hlbm.h -- C ABI of the MI355X (gfx950) hybrid lattice-Boltzmann library.
+ *
+ * One time step of the D2Q9 hybrid LBM of Renard, Feng, Boussuge and Sagaut
+ * (arXiv 2002.03644): regularised (HRR) collision with the lattice-closure
+ * correction psi (upwind E1 plus the polyatomic E2, Sec. 3.2), the recursive
+ * off-equilibrium reconstruction (Sec. 3.3), streaming (Sec. 3.1), and the
+ * finite-volume entropy update with the viscous heat production from the
+ * regularised stress (Sec. 3.4), closed by p = rho c_s^2 theta and
+ * s = c_v ln(theta / rho^(gamma-1)) (Sec. 2.1, 2.4).  The step order follows
+ * the algorithm of Sec. 3.5.  Lattice units: Dx = Dt = 1, c_s^2 = 1/3.
+ *
+ * Conventions for every entry point
+ *  - Fields are row-major [ny][nx] arrays, x fastest, contiguous; populations
+ *    are nine such planes [9][ny][nx] in the lattice order
+ *    c_x = {0,1,0,-1,0,1,-1,-1,1}, c_y = {0,0,1,0,-1,1,1,-1,-1}.
+ *  - Array pointers are DEVICE pointers unless the name says host_.  Their
+ *    element type is the handle's dtype (double for HLBM_F64, float for
+ *    HLBM_F32).
+ *  - The caller owns every device buffer, including the workspace; the library
+ *    never allocates device memory.  The library owns only its small host
+ *    handle, released by the matching destroy call.
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL is the
+ *    default stream) and is asynchronous unless stated otherwise.
+ *  - Errors are negative return codes (hlbm_status_code); nothing throws across the
+ *    ABI.  A HIP launch failure is reported as HLBM_EHIP.
+ *  - Calls on one handle must not overlap in time from several host threads.
+ */
+#ifndef HLBM_H
+#define HLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *hlbm_stream_t; /* a hipStream_t */
+
+typedef enum {
+  HLBM_OK = 0,
+  HLBM_WARN_CFL = 1,     /* init succeeded, but the largest local CFL number
+                            (|u| + sqrt(gamma c_s^2 theta), Sec. 3.5) is >= 1 */
+  HLBM_EINVAL = -1,      /* invalid parameter, size or pointer */
+  HLBM_EWORKSPACE = -2,  /* workspace missing or smaller than required */
+  HLBM_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
+  HLBM_EDIVERGED = -4,   /* non-finite value, rho <= 0 or theta <= 0 found */
+  HLBM_ENOMEM = -5       /* host allocation of the handle failed */
+} hlbm_status_code;
+
+typedef enum { HLBM_BC_PERIODIC = 0, HLBM_BC_EXTRAPOLATE = 1 } hlbm_bc;
+typedef enum { HLBM_F64 = 0, HLBM_F32 = 1 } hlbm_dtype;
+typedef enum { HLBM_PHI_LBM = 0, HLBM_PHI_FD = 1 } hlbm_phi;
+
+/* Parameters of one domain.  A zero-initialised struct plus nx, ny, gamma,
+ * prandtl and the reference state selects the present model. */
+typedef struct {
+  int32_t nx, ny;       /* grid size, >= 1 each, 9 * nx * ny < 2^31 */
+  int32_t bc_x, bc_y;   /* hlbm_bc on both sides of that axis: periodic wrap,
+                           or zero-gradient extrapolation (the neighbour index
+                           is clamped into the grid, so ghost nodes carry the
+                           full state of the nearest boundary node) */
+  int32_t dtype;        /* hlbm_dtype of every array passed in or out */
+  int32_t phi_mode;     /* viscous heat Phi: HLBM_PHI_LBM = -(tau/taubar) a1 : grad u
+                           (Eq. viscous heat discret), HLBM_PHI_FD = finite
+                           differences (Eq. viscous heat; for discontinuities) */
+  int32_t e1_centred;   /* 0: upwind E1 of Sec. 3.2 (present model);
+                           1: centred E1 (original-model ablation) */
+  int32_t e2_off;       /* 0: with the polyatomic E2 term (present model);
+                           1: without it (original-model ablation) */
+  int32_t tile_w;       /* workgroup width in threads (64, 128 or 256), 0 = auto */
+  int32_t tile_h;       /* output rows per workgroup strip (>= 1), 0 = auto */
+  double gamma;         /* heat-capacity ratio, > 1 */
+  double prandtl;       /* Prandtl number, > 0; lambda = mu c_p / Pr */
+  double mu;            /* dynamic viscosity, >= 0; local tau = mu / p */
+  double sigma;         /* HRR blend in [0, 1] (Eq. a1sigalgo) */
+  double rho_ref;       /* HLBM_F32 storage reference density, > 0 */
+  double theta_ref;     /* HLBM_F32 storage reference temperature, > 0 */
+  double sgn_eps;       /* >= 0: the upwind E1 of Sec. 3.2 takes sgn(u) = 0 (centred
+                           difference) for |u| <= sgn_eps.  0 is the literal sign,
+                           which is discontinuous at u = 0; 1e-12 keeps
+                           rounding-level velocities from flipping the stencil */
+} hlbm_params;
+
+typedef struct hlbm_handle hlbm_handle;
+
+/* Bytes of device workspace a domain with these parameters needs (two state
+ * buffers of ten planes plus reduction scratch), or 0 if the parameters are
+ * invalid.  Host-only; callable without a GPU. */
+size_t hlbm_workspace_bytes(const hlbm_params *p);
+
+/* Bytes of one raw state copy (ten planes, storage format) for
+ * hlbm_save_state / hlbm_load_state; 0 if invalid.  Host-only. */
+size_t hlbm_state_bytes(const hlbm_params *p);
+
+/* Check parameters without touching the GPU: HLBM_OK or HLBM_EINVAL. */
+int hlbm_validate(const hlbm_params *p);
+
+/* Initialise a domain from macroscopic fields (algorithm of Sec. 3.5, steps
+ * 1-4): F0 = f^eq + f^1[a1FD] - psi/2 at every node, so the first step sees
+ * the finite-difference off-equilibrium stress for any sigma.
+ *   out        receives a new host handle (set to NULL on error)
+ *   workspace  device buffer of at least hlbm_workspace_bytes(p) bytes, owned
+ *              by the caller, that must outlive the handle
+ *   rho, ux, uy, s  device [ny][nx] arrays (dtype of p): density, velocity,
+ *              entropy s = c_v ln(theta / rho^(gamma-1))
+ * Synchronises `stream` once to evaluate the initial CFL number.  Returns
+ * HLBM_OK, HLBM_WARN_CFL (initialised; max local CFL >= 1), or an error. */
+int hlbm_init(hlbm_handle **out, const hlbm_params *p, void *workspace, size_t ws_bytes,
+              const void *rho, const void *ux, const void *uy, const void *s,
+              hlbm_stream_t stream);
+
+/* Enqueue nsteps (>= 0) time steps (Sec. 3.5, steps 5-11).  Asynchronous. */
+int hlbm_step(hlbm_handle *h, int32_t nsteps, hlbm_stream_t stream);
+
+/* Write the macroscopic fields of the current state: rho = sum F,
+ * rho u = sum c F (Eqs. rhoalgo, ualgo), s, and theta from s and rho.
+ * Any output pointer may be NULL.  Asynchronous. */
+int hlbm_moments(hlbm_handle *h, void *rho, void *ux, void *uy, void *s, void *theta,
+                 hlbm_stream_t stream);
+
+/* Absolute populations F_i, device [9][ny][nx] in the handle's dtype
+ * (HLBM_F32 storage deviations are added back to the reference).  Async. */
+int hlbm_populations(hlbm_handle *h, void *F9, hlbm_stream_t stream);
+
+/* Replace the state by absolute populations F9 [9][ny][nx] and entropy s
+ * [ny][nx] (device, handle dtype).  Asynchronous. */
+int hlbm_set_populations(hlbm_handle *h, const void *F9, const void *s, hlbm_stream_t stream);
+
+/* Conservation totals in FP64, accumulated in a fixed order (deterministic):
+ * host_out4 = {sum rho, sum rho u_x, sum rho u_y, sum(rho c_v theta +
+ * rho |u|^2 / 2)}.  Synchronises `stream`. */
+int hlbm_totals(hlbm_handle *h, double *host_out4, hlbm_stream_t stream);
+
+/* Divergence check over the current state: HLBM_OK, or HLBM_EDIVERGED if any
+ * node holds a non-finite value, rho <= 0 or theta <= 0.  If host_max_cfl is
+ * not NULL it receives the largest local CFL number.  Synchronises `stream`. */
+int hlbm_status(hlbm_handle *h, double *host_max_cfl, hlbm_stream_t stream);
+
+/* Raw state copy for checkpoint / resume (bit-exact).  dst / src are device
+ * buffers of hlbm_state_bytes(p) bytes.  Asynchronous. */
+int hlbm_save_state(hlbm_handle *h, void *dst, hlbm_stream_t stream);
+int hlbm_load_state(hlbm_handle *h, const void *src, hlbm_stream_t stream);
+
+/* Number of steps taken since init (host counter). */
+int64_t hlbm_steps_done(const hlbm_handle *h);
+
+/* Release the host handle (the workspace stays the caller's). */
+void hlbm_destroy(hlbm_handle *h);
+
+/* Static message for a status code. */
+const char *hlbm_strerror(int code);
+
+/* Entropy from temperature, s = c_v ln(theta / rho^(gamma-1)) with
+ * c_v = c_s^2 / (gamma - 1) (Sec. 2.1, 2.4), over n device elements of
+ * `dtype`.  Asynchronous. */
+int hlbm_entropy_from_theta(int32_t dtype, double gamma, const void *rho, const void *theta,
+                            void *s, int64_t n, hlbm_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HLBM_H */

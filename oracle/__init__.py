@@ -38,7 +38,8 @@ class _Params(ctypes.Structure):
                 ("phi_mode", ctypes.c_int32), ("e1_centred", ctypes.c_int32),
                 ("e2_off", ctypes.c_int32), ("feq_order", ctypes.c_int32),
                 ("gamma", ctypes.c_double), ("prandtl", ctypes.c_double),
-                ("mu", ctypes.c_double), ("sigma", ctypes.c_double)]
+                ("mu", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("sgn_eps", ctypes.c_double)]
 
 
 _lib = None
@@ -142,11 +143,12 @@ class OracleParams:
     e1_centred: bool = False
     e2_off: bool = False
     feq_order: int = 4
+    sgn_eps: float = 1e-12
 
     def c(self):
         return _Params(self.nx, self.ny, BC[self.bc_x], BC[self.bc_y], PHI[self.phi_mode],
                        int(self.e1_centred), int(self.e2_off), int(self.feq_order),
-                       self.gamma, self.prandtl, self.mu, self.sigma)
+                       self.gamma, self.prandtl, self.mu, self.sigma, self.sgn_eps)
 
 
 class OracleSolver:

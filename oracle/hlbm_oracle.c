@@ -31,7 +31,9 @@
  * Readings of points the paper leaves open (each is listed with its reason in
  * the design notes): constant mu, local tau = mu / p; lambda = mu c_p / Pr;
  * sgn(0) = 0 in E1 (centred average); non-conservative MUSCL with node-sign
- * upwinding and the van Albada slope; 5-point Laplacian for the Fourier term;
+ * upwinding and the van Albada slope; sgn(u) in E1 is 0 inside a rounding
+ * band |u| <= sgn_eps (the literal sign is discontinuous at u = 0 and turns
+ * rounding noise into O(dGamma) jumps at wave fronts); 5-point Laplacian for the Fourier term;
  * boundaries per axis either periodic or zero-gradient (ghost = copy of the
  * nearest interior node state).
  *
@@ -59,6 +61,7 @@ typedef struct {
   int32_t e2_off;       /* ablation: 1 = no E2 term (original model) */
   int32_t feq_order;    /* 4 (present model) or 3 (original model) */
   double gamma, prandtl, mu, sigma;
+  double sgn_eps;       /* |u| <= sgn_eps counts as sgn(u) = 0 in E1 (0: literal sign) */
 } ora_params;
 
 /* ------------------------------------------------------------------------- */
@@ -420,9 +423,11 @@ static void gradient_pass(ora_state *S) {
       S->dxuy[k] = 0.5 * (S->uy[e] - S->uy[w]);
       S->dyuy[k] = 0.5 * (S->uy[n] - S->uy[so]);
       double div = S->dxux[k] + S->dyuy[k];
-      /* E1_xx: [1+sgn(ux)]/2 (G_i - G_{i-1}) + [1-sgn(ux)]/2 (G_{i+1} - G_i) */
-      double sx = (S->ux[k] > 0.0) ? 1.0 : ((S->ux[k] < 0.0) ? -1.0 : 0.0);
-      double sy = (S->uy[k] > 0.0) ? 1.0 : ((S->uy[k] < 0.0) ? -1.0 : 0.0);
+      /* E1_xx: [1+sgn(ux)]/2 (G_i - G_{i-1}) + [1-sgn(ux)]/2 (G_{i+1} - G_i);
+       * a velocity within the rounding band |u| <= sgn_eps has sign 0. */
+      const double eps = S->p.sgn_eps;
+      double sx = (S->ux[k] > eps) ? 1.0 : ((S->ux[k] < -eps) ? -1.0 : 0.0);
+      double sy = (S->uy[k] > eps) ? 1.0 : ((S->uy[k] < -eps) ? -1.0 : 0.0);
       if (S->p.e1_centred) {
         sx = 0.0;
         sy = 0.0;

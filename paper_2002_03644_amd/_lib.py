@@ -1,0 +1,255 @@
+"""ctypes binding of libhlbm.so (declared in include/hlbm.h).
+
+Argument marshalling only: PyTorch provides device memory and the stream;
+every step of the method runs in the library's HIP kernels.  There is no CPU
+fallback -- if the library is missing or no GPU is present, calls fail.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhlbm.so")
+
+HLBM_OK, HLBM_WARN_CFL = 0, 1
+HLBM_EINVAL, HLBM_EWORKSPACE, HLBM_EHIP, HLBM_EDIVERGED, HLBM_ENOMEM = -1, -2, -3, -4, -5
+F64, F32 = 0, 1
+BC = {"periodic": 0, "extrapolate": 1}
+PHI = {"lbm": 0, "fd": 1}
+
+
+class HlbmError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} (code {code})")
+
+
+class CParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("phi_mode", ctypes.c_int32),
+                ("e1_centred", ctypes.c_int32), ("e2_off", ctypes.c_int32),
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("prandtl", ctypes.c_double),
+                ("mu", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("rho_ref", ctypes.c_double), ("theta_ref", ctypes.c_double),
+                ("sgn_eps", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhlbm.so (built by paper_2002_03644_amd.build); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2002_03644_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        PP = ctypes.POINTER(CParams)
+        dp = ctypes.POINTER(ctypes.c_double)
+        sig = {
+            "hlbm_workspace_bytes": (sz, [PP]),
+            "hlbm_state_bytes": (sz, [PP]),
+            "hlbm_validate": (ctypes.c_int, [PP]),
+            "hlbm_init": (ctypes.c_int, [ctypes.POINTER(vp), PP, vp, sz, vp, vp, vp, vp, vp]),
+            "hlbm_step": (ctypes.c_int, [vp, i32, vp]),
+            "hlbm_moments": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+            "hlbm_populations": (ctypes.c_int, [vp, vp, vp]),
+            "hlbm_set_populations": (ctypes.c_int, [vp, vp, vp, vp]),
+            "hlbm_totals": (ctypes.c_int, [vp, dp, vp]),
+            "hlbm_status": (ctypes.c_int, [vp, dp, vp]),
+            "hlbm_save_state": (ctypes.c_int, [vp, vp, vp]),
+            "hlbm_load_state": (ctypes.c_int, [vp, vp, vp]),
+            "hlbm_steps_done": (i64, [vp]),
+            "hlbm_destroy": (None, [vp]),
+            "hlbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+            "hlbm_entropy_from_theta": (ctypes.c_int, [i32, ctypes.c_double, vp, vp, vp, i64, vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().hlbm_strerror(int(code)).decode()
+    except ImportError:
+        return f"status {code}"
+
+
+def _check(code, what):
+    if code < 0:
+        raise HlbmError(code, what)
+    return code
+
+
+@dataclass
+class Params:
+    """Parameters of one domain (mirror of hlbm_params)."""
+    nx: int
+    ny: int
+    dtype: str = "f64"
+    gamma: float = 1.4
+    prandtl: float = 0.71
+    mu: float = 1e-3
+    sigma: float = 0.0
+    bc_x: str = "periodic"
+    bc_y: str = "periodic"
+    phi_mode: str = "lbm"
+    e1_centred: bool = False
+    e2_off: bool = False
+    rho_ref: float = 1.0
+    theta_ref: float = 240.0 / 1183.0
+    tile_w: int = 0
+    tile_h: int = 0
+    sgn_eps: float = 1e-12
+
+    def c(self) -> CParams:
+        return CParams(self.nx, self.ny, BC[self.bc_x], BC[self.bc_y],
+                       F64 if self.dtype == "f64" else F32, PHI[self.phi_mode],
+                       int(self.e1_centred), int(self.e2_off), int(self.tile_w), int(self.tile_h),
+                       self.gamma, self.prandtl, self.mu, self.sigma, self.rho_ref, self.theta_ref,
+                       self.sgn_eps)
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.dtype == "f64" else torch.float32
+
+
+def validate(p: Params) -> int:
+    cp = p.c()
+    return lib().hlbm_validate(ctypes.byref(cp))
+
+
+def workspace_bytes(p: Params) -> int:
+    cp = p.c()
+    return int(lib().hlbm_workspace_bytes(ctypes.byref(cp)))
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dev_field(a, p: Params, device):
+    import torch
+    t = torch.as_tensor(a)
+    t = t.to(device=device, dtype=p.torch_dtype).contiguous()
+    if t.numel() != p.nx * p.ny:
+        raise ValueError("field size does not match nx * ny")
+    return t.reshape(p.ny, p.nx)
+
+
+def entropy_from_theta(rho, theta, gamma, dtype="f64", device="cuda"):
+    """s = c_v ln(theta / rho^(gamma - 1)) on the GPU."""
+    import torch
+    td = torch.float64 if dtype == "f64" else torch.float32
+    r = torch.as_tensor(rho).to(device=device, dtype=td).contiguous()
+    th = torch.as_tensor(theta).to(device=device, dtype=td).contiguous()
+    s = torch.empty_like(r)
+    _check(lib().hlbm_entropy_from_theta(F64 if dtype == "f64" else F32, float(gamma), _ptr(r),
+                                         _ptr(th), _ptr(s), r.numel(), _stream()),
+           "hlbm_entropy_from_theta")
+    return s
+
+
+class Solver:
+    """One HLBM domain on the GPU.  Fields are torch tensors (or numpy arrays,
+    copied to the device); either s or theta is given."""
+
+    def __init__(self, params: Params, rho, ux, uy, s=None, theta=None, device="cuda"):
+        import torch
+        self.p = params
+        self.device = torch.device(device)
+        rho = _dev_field(rho, params, self.device)
+        ux = _dev_field(ux, params, self.device)
+        uy = _dev_field(uy, params, self.device)
+        if s is None:
+            th = _dev_field(theta, params, self.device)
+            s = entropy_from_theta(rho, th, params.gamma, params.dtype, self.device)
+        s = _dev_field(s, params, self.device)
+        self._cp = params.c()
+        nbytes = lib().hlbm_workspace_bytes(ctypes.byref(self._cp))
+        if nbytes == 0:
+            raise HlbmError(HLBM_EINVAL, "hlbm_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        code = lib().hlbm_init(ctypes.byref(h), ctypes.byref(self._cp), _ptr(self.workspace),
+                               nbytes, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(s), _stream())
+        _check(code, "hlbm_init")
+        self.init_code = code
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().hlbm_destroy(h)
+            self.h = None
+
+    @property
+    def steps(self) -> int:
+        return int(lib().hlbm_steps_done(self.h))
+
+    def step(self, n=1, stream=None):
+        _check(lib().hlbm_step(self.h, int(n), _stream(stream)), "hlbm_step")
+        return self
+
+    def _empty(self, *shape):
+        import torch
+        return torch.empty(*shape, dtype=self.p.torch_dtype, device=self.device)
+
+    def moments(self):
+        out = {k: self._empty(self.p.ny, self.p.nx) for k in ("rho", "ux", "uy", "s", "theta")}
+        _check(lib().hlbm_moments(self.h, _ptr(out["rho"]), _ptr(out["ux"]), _ptr(out["uy"]),
+                                  _ptr(out["s"]), _ptr(out["theta"]), _stream()), "hlbm_moments")
+        return out
+
+    def populations(self):
+        F = self._empty(9, self.p.ny, self.p.nx)
+        _check(lib().hlbm_populations(self.h, _ptr(F), _stream()), "hlbm_populations")
+        return F
+
+    def set_populations(self, F, s):
+        import torch
+        F = torch.as_tensor(F).to(self.device, self.p.torch_dtype).contiguous()
+        s = torch.as_tensor(s).to(self.device, self.p.torch_dtype).contiguous()
+        _check(lib().hlbm_set_populations(self.h, _ptr(F), _ptr(s), _stream()),
+               "hlbm_set_populations")
+
+    def totals(self):
+        out = (ctypes.c_double * 4)()
+        _check(lib().hlbm_totals(self.h, out, _stream()), "hlbm_totals")
+        return np.array(out[:])
+
+    def status(self):
+        cfl = ctypes.c_double(0.0)
+        code = lib().hlbm_status(self.h, ctypes.byref(cfl), _stream())
+        if code not in (HLBM_OK, HLBM_EDIVERGED):
+            raise HlbmError(code, "hlbm_status")
+        return code, cfl.value
+
+    def save_state(self):
+        import torch
+        n = lib().hlbm_state_bytes(ctypes.byref(self._cp))
+        buf = torch.empty(n, dtype=torch.uint8, device=self.device)
+        _check(lib().hlbm_save_state(self.h, _ptr(buf), _stream()), "hlbm_save_state")
+        return buf
+
+    def load_state(self, buf):
+        _check(lib().hlbm_load_state(self.h, _ptr(buf), _stream()), "hlbm_load_state")

@@ -1,0 +1,131 @@
+// Launchers of one precision; included by hlbm_kernels_f32.hip and
+// hlbm_kernels_f64.hip after HLBM_REAL and HLBM_NS are defined.
+#include "hlbm_device.hpp"
+#include "hlbm_launch.hpp"
+
+namespace hlbm {
+namespace HLBM_NS {
+
+static DomainArgs to_device(const HostDomain &h) {
+  DomainArgs d;
+  d.plane = h.plane;
+  d.nx = h.nx;
+  d.ny = h.ny;
+  d.bcx = h.bcx;
+  d.bcy = h.bcy;
+  d.flags = h.flags;
+  d.mu = (real)h.mu;
+  d.sigma = (real)h.sigma;
+  d.lambda = (real)h.lambda;
+  d.inv_cv = (real)h.inv_cv;
+  d.gm1 = (real)h.gm1;
+  d.e2c = (real)h.e2c;
+  d.gamma = (real)h.gamma;
+  d.sgn_eps = (real)h.sgn_eps;
+  d.rho_ref = (real)h.rho_ref;
+  d.theta_ref = (real)h.theta_ref;
+  d.log_rho_ref = (real)h.log_rho_ref;
+  d.s_ref = (real)h.s_ref;
+  for (int q = 0; q < kQ; ++q) d.fref[q] = (real)h.fref[q];
+  return d;
+}
+
+static int grid_for(long long n, int threads) {
+  long long b = (n + threads - 1) / threads;
+  if (b > 65536) b = 65536;
+  return (int)(b < 1 ? 1 : b);
+}
+
+hipError_t step(const HostDomain &h, const void *src, void *dst, unsigned *status,
+                const TileShape &tile, hipStream_t st) {
+  StepArgs a;
+  a.d = to_device(h);
+  a.src = (const real *)src;
+  a.dst = (real *)dst;
+  a.status = status;
+  a.rows = tile.rows;
+  a.ow = tile.bw - 4;
+  a.nbx = (h.nx + a.ow - 1) / a.ow;
+  a.nby = (h.ny + tile.rows - 1) / tile.rows;
+  a.xcd_remap = tile.xcd_remap;
+  const int nblk = a.nbx * a.nby;
+  switch (tile.bw) {
+  case 64:
+    hipLaunchKernelGGL(k_step<64>, dim3(nblk), dim3(64), 0, st, a);
+    break;
+  case 128:
+    hipLaunchKernelGGL(k_step<128>, dim3(nblk), dim3(128), 0, st, a);
+    break;
+  case 256:
+    hipLaunchKernelGGL(k_step<256>, dim3(nblk), dim3(256), 0, st, a);
+    break;
+  default:
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t init(const HostDomain &h, const void *rho, const void *ux, const void *uy,
+                const void *s, void *dst, hipStream_t st) {
+  InitArgs a;
+  a.d = to_device(h);
+  a.rho = (const real *)rho;
+  a.ux = (const real *)ux;
+  a.uy = (const real *)uy;
+  a.s = (const real *)s;
+  a.dst = (real *)dst;
+  const long long n = (long long)h.nx * h.ny;
+  hipLaunchKernelGGL(k_init, dim3(grid_for(n, 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t moments(const HostDomain &h, const void *state, void *rho, void *ux, void *uy,
+                   void *s, void *theta, hipStream_t st) {
+  FieldArgs a;
+  a.d = to_device(h);
+  a.state = (const real *)state;
+  a.rho = (real *)rho;
+  a.ux = (real *)ux;
+  a.uy = (real *)uy;
+  a.s = (real *)s;
+  a.theta = (real *)theta;
+  const long long n = (long long)h.nx * h.ny;
+  hipLaunchKernelGGL(k_moments, dim3(grid_for(n, 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t populations(const HostDomain &h, void *state, void *F9, const void *s, int to_state,
+                       hipStream_t st) {
+  PopArgs a;
+  a.d = to_device(h);
+  a.state = (real *)state;
+  a.F9 = (real *)F9;
+  a.s = (real *)s;
+  a.to_state = to_state;
+  const long long n = (long long)h.nx * h.ny;
+  hipLaunchKernelGGL(k_populations, dim3(grid_for(n, 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t reduce(const HostDomain &h, const void *state, double *partials, int nparts,
+                  double *out, hipStream_t st) {
+  ReduceArgs a;
+  a.d = to_device(h);
+  a.state = (const real *)state;
+  a.partials = partials;
+  hipLaunchKernelGGL(k_reduce, dim3(nparts), dim3(kRedThreads), 0, st, a);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, st, (const double *)partials,
+                     nparts, out);
+  return hipGetLastError();
+}
+
+hipError_t entropy(const void *rho, const void *theta, void *s, long long n, double gamma,
+                   hipStream_t st) {
+  const double cv = kCs2 / (gamma - 1.0);
+  hipLaunchKernelGGL(k_entropy, dim3(grid_for(n, 256)), dim3(256), 0, st, (const real *)rho,
+                     (const real *)theta, (real *)s, n, (real)(1.0 / cv), (real)(gamma - 1.0));
+  return hipGetLastError();
+}
+
+}  // namespace HLBM_NS
+}  // namespace hlbm

@@ -1,0 +1,47 @@
+// Host-side launch interface between the C ABI (hlbm_api.cpp) and the
+// per-precision kernel translation units.  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace hlbm {
+
+// Domain description in host precision; each translation unit converts it
+// to its device argument struct.
+struct HostDomain {
+  long long plane;
+  int nx, ny, bcx, bcy, flags;
+  double mu, sigma, lambda, inv_cv, gm1, e2c, gamma, sgn_eps;
+  double rho_ref, theta_ref, log_rho_ref, s_ref;
+  double fref[9];
+};
+
+struct TileShape {
+  int bw;        // threads per workgroup: 64, 128 or 256
+  int rows;      // output rows per strip
+  int xcd_remap; // 0 or 1
+};
+
+#define HLBM_DECLARE_LAUNCHERS(NS)                                                          \
+  namespace NS {                                                                            \
+  hipError_t step(const HostDomain &d, const void *src, void *dst, unsigned *status,        \
+                  const TileShape &tile, hipStream_t st);                                   \
+  hipError_t init(const HostDomain &d, const void *rho, const void *ux, const void *uy,     \
+                  const void *s, void *dst, hipStream_t st);                                \
+  hipError_t moments(const HostDomain &d, const void *state, void *rho, void *ux, void *uy, \
+                     void *s, void *theta, hipStream_t st);                                 \
+  hipError_t populations(const HostDomain &d, void *state, void *F9, const void *s,         \
+                         int to_state, hipStream_t st);                                     \
+  hipError_t reduce(const HostDomain &d, const void *state, double *partials, int nparts,   \
+                    double *out, hipStream_t st);                                           \
+  hipError_t entropy(const void *rho, const void *theta, void *s, long long n, double gamma, \
+                     hipStream_t st);                                                       \
+  }
+
+HLBM_DECLARE_LAUNCHERS(f32)
+HLBM_DECLARE_LAUNCHERS(f64)
+
+constexpr int kReduceParts = 1024;  // workgroups of the first reduction pass
+constexpr int kReduceVals = 6;
+
+}  // namespace hlbm

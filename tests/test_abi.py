@@ -1,0 +1,90 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+symbol include/hlbm.h declares, and its host-only functions validate
+parameters and size workspaces."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hlbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(hlbm_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_core_entry_points():
+    names = declared_functions()
+    for n in ("hlbm_init", "hlbm_step", "hlbm_moments", "hlbm_totals", "hlbm_status",
+              "hlbm_destroy", "hlbm_workspace_bytes"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2002_03644_amd import _lib
+    L = _lib.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def _params(**kw):
+    from paper_2002_03644_amd import Params
+    base = dict(nx=64, ny=32, dtype="f32")
+    base.update(kw)
+    return Params(**base)
+
+
+def test_validate_accepts_defaults():
+    from paper_2002_03644_amd import HLBM_OK, validate
+    assert validate(_params()) == HLBM_OK
+    assert validate(_params(dtype="f64", bc_x="extrapolate", phi_mode="fd")) == HLBM_OK
+
+
+@pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-3), dict(gamma=1.0), dict(prandtl=0.0),
+                                 dict(mu=-1e-3), dict(sigma=1.5), dict(rho_ref=0.0),
+                                 dict(theta_ref=-1.0), dict(tile_w=96), dict(tile_h=-1),
+                                 dict(nx=20000, ny=20000), dict(mu=float("nan"))])
+def test_validate_rejects(bad):
+    from paper_2002_03644_amd import HLBM_EINVAL, validate, workspace_bytes
+    p = _params(**bad)
+    assert validate(p) == HLBM_EINVAL
+    assert workspace_bytes(p) == 0
+
+
+def test_workspace_size_covers_two_state_buffers():
+    from paper_2002_03644_amd import workspace_bytes
+    for dt, es in (("f32", 4), ("f64", 8)):
+        for nx, ny in ((8192, 8192), (4096, 4), (1, 1), (131, 77)):
+            ws = workspace_bytes(_params(nx=nx, ny=ny, dtype=dt))
+            assert ws >= 2 * 10 * nx * ny * es
+            assert ws < 2 * 10 * (nx * ny + 64) * es + 2 * 2 ** 20
+
+
+def test_largest_grid_accepted():
+    from paper_2002_03644_amd import HLBM_OK, validate
+    assert validate(_params(nx=15446, ny=15446)) == HLBM_OK  # 9 n^2 < 2^31
+    assert validate(_params(nx=15447, ny=15447)) != HLBM_OK
+
+
+def test_init_rejects_null_and_small_workspace():
+    from paper_2002_03644_amd import _lib
+    L = _lib.lib()
+    cp = _params().c()
+    h = ctypes.c_void_p()
+    code = L.hlbm_init(ctypes.byref(h), ctypes.byref(cp), None, 0, None, None, None, None, None)
+    assert code == _lib.HLBM_EINVAL
+    fake = ctypes.c_void_p(256)  # never dereferenced: rejected before any launch
+    code = L.hlbm_init(ctypes.byref(h), ctypes.byref(cp), fake, 16, fake, fake, fake, fake, None)
+    assert code == _lib.HLBM_EWORKSPACE
+    assert not h.value
+
+
+def test_strerror_covers_codes():
+    from paper_2002_03644_amd import strerror
+    for c in (0, 1, -1, -2, -3, -4, -5):
+        assert strerror(c) and "unknown" not in strerror(c)

@@ -156,3 +156,24 @@ def test_entropy_closure_roundtrip():
     np.testing.assert_allclose(m["rho"], r, rtol=1e-13)
     np.testing.assert_allclose(m["ux"], u, atol=1e-14)
     np.testing.assert_allclose(m["uy"], v, atol=1e-14)
+
+
+def test_f1_recursion_is_galilean_shift():
+    """The recursion of Sec. 3.3 is the binomial (Galilean) shift of a purely
+    second-order off-equilibrium moment from the fluid frame to the lab
+    frame, plus the thermal trace part: the lab-frame xxy, yyx and xxyy
+    Hermite moments of f^1 are u_y a_xx + 2 u_x a_xy, u_x a_yy + 2 u_y a_xy
+    and u_y^2 a_xx + u_x^2 a_yy + 4 u_x u_y a_xy + c_s^2 (theta - 1) tr a."""
+    for _ in range(8):
+        axx, axy, ayy = rng.normal(size=3) * 1e-2
+        ux, uy = rng.uniform(-0.5, 0.5, size=2)
+        th = rng.uniform(0.1, 1.2)
+        f = oracle.f1(axx, axy, ayy, ux, uy, th)
+        np.testing.assert_allclose((HXX * f).sum(), axx, atol=1e-15)
+        np.testing.assert_allclose((HXY * f).sum(), axy, atol=1e-15)
+        np.testing.assert_allclose((HYY * f).sum(), ayy, atol=1e-15)
+        np.testing.assert_allclose((HXXY * f).sum(), uy * axx + 2 * ux * axy, atol=1e-15)
+        np.testing.assert_allclose((HXYY * f).sum(), ux * ayy + 2 * uy * axy, atol=1e-15)
+        shift = uy * uy * axx + ux * ux * ayy + 4 * ux * uy * axy
+        thermal = CS2 * (th - 1.0) * (axx + ayy)
+        np.testing.assert_allclose((HXXYY * f).sum(), shift + thermal, atol=1e-15)

@@ -294,3 +294,25 @@ def test_normal_shock_jump_conditions():
     ex = hi.rankine_hugoniot(2.0)
     t_ratio = m["theta"][:, down].mean() / m["theta"][:, up].mean()
     assert 0.87 * ex[3] < t_ratio < ex[3]
+
+
+@pytest.mark.parametrize("mach", [1.0, 1.5])
+def test_original_model_diverges_present_model_stable(mach):
+    """Table 1: the original model (centred E1) diverges for Ma >= 1 in the
+    shear-wave case while the present model (upwind E1) stays stable."""
+    n, theta, nu = 200, 0.375, 0.0240918
+    c = hi.sound_speed(1.4, theta)
+    fields = hi.shear_wave(n, 0.0240918, mach * c, theta)
+
+    def survives(**kw):
+        S = oracle.OracleSolver(oracle.OracleParams(2, n, mu=nu, sigma=0.0, **kw), *fields[:3],
+                                theta=fields[3])
+        for _ in range(8):
+            S.step(200)
+            m = S.moments()
+            if not np.isfinite(m["rho"]).all() or np.abs(m["ux"]).max() > 1.0:
+                return False
+        return True
+
+    assert survives()
+    assert not survives(e1_centred=True, e2_off=True, feq_order=3)
