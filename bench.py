@@ -27,7 +27,7 @@ METRIC = ("HLBM MLUPS & % HBM roofline @8192² FP32; learned-vs-plain time at eq
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
 BYTES_PER_NODE = 80            # read 9 populations + s, write 9 + s, FP32
 KERNEL_SRC = os.path.join(ROOT, "paper_2002_03644_amd", "csrc", "hlbm_device.hpp")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_f32_turbulence8192_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_f32_turbulence8192_traffic.txt")
 
 
 def kernel_hash() -> str:
@@ -36,19 +36,24 @@ def kernel_hash() -> str:
 
 
 def measured_traffic(nodes: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source (else None)."""
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (lines `key: value`), if it was taken on the current kernel source at
+    this grid size; else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            t = json.load(fh)
-    except (OSError, ValueError):
+            kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
+    except OSError:
         return None
-    if t.get("kernel_source_sha256_16") != kernel_hash() or t.get("nodes") != nodes:
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_source_sha256_16") != kernel_hash() or kv.get("nodes") != str(nodes):
         return None
-    return t.get("bytes_per_launch")
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
-def cpu_baseline(n_sample=1024, steps=12):
+def cpu_baseline(n_sample=1024, steps=150):
     """The FP64 oracle on an n_sample^2 periodic window of the same
     turbulence recipe, timed on the host cores (steady-state steps only)."""
     import numpy as np
@@ -132,9 +137,11 @@ def main():
                 "traffic": traffic}
 
     if args.copy_calibration:
-        a = torch.empty(2 ** 31, dtype=torch.uint8, device=dev)
+        # a plain elementwise copy kernel moving 2 GiB in and 2 GiB out, whose
+        # counter readings calibrate FETCH_SIZE / WRITE_SIZE
+        a = torch.zeros(2 ** 29, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
         del a, b
 

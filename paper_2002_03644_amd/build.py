@@ -21,7 +21,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
 
 UNITS = {
     "hlbm_api.hip": [],
-    "hlbm_kernels_f32.hip": [],
+    "hlbm_kernels_f32.hip": ["-ffp-contract=on"],
     "hlbm_kernels_f64.hip": ["-ffp-contract=off"],
 }
 

@@ -82,8 +82,10 @@ void rest_equilibrium(double rho, double theta, double f[9]) {
 
 hlbm::TileShape default_tile(const hlbm_params *p) {
   hlbm::TileShape t;
-  t.bw = p->tile_w ? p->tile_w : (p->dtype == HLBM_F64 ? 64 : 128);
-  int rows = p->tile_h ? p->tile_h : (p->dtype == HLBM_F64 ? 32 : 64);
+  // 128-column tiles with 32-row strips measured fastest at 8192^2 in FP32
+  // (aligned row segments, 21 resident waves per CU).
+  t.bw = p->tile_w ? p->tile_w : 128;
+  int rows = p->tile_h ? p->tile_h : 32;
   if (rows > p->ny) rows = p->ny;
   t.rows = rows;
   t.xcd_remap = 1;

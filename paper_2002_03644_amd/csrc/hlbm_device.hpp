@@ -54,11 +54,10 @@ struct DomainArgs {
 
 struct StepArgs {
   DomainArgs d;
-  const real *__restrict__ src;
-  real *__restrict__ dst;
+  const real *src[kPlanes];  // per-plane base pointers (uniform: SGPR operands)
+  real *dst[kPlanes];
   unsigned *status;    // bit 0 set when a node diverged
   int rows;            // output rows per strip
-  int ow;              // output columns per workgroup (tile width - 4)
   int nbx, nby;        // workgroups along x and y
   int xcd_remap;       // 1: spread spatial neighbours onto the same XCD
 };
@@ -86,6 +85,20 @@ __device__ __forceinline__ float sqrt_r(float x) { return __builtin_sqrtf(x); }
 __device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
 
 constexpr double kCs2 = 1.0 / 3.0;
+
+// Global access through a uniform base pointer and a 32-bit byte offset, so
+// the address is SGPR base + VGPR offset (no 64-bit address arithmetic).
+__device__ __forceinline__ real load_at(const real *base, unsigned byte_off) {
+  return *(const real *)((const char *)base + byte_off);
+}
+__device__ __forceinline__ void store_at(real *base, unsigned byte_off, real v) {
+  *(real *)((char *)base + byte_off) = v;
+}
+// Streaming store: the new state is not read again before the whole grid is
+// written, so it bypasses cache retention.
+__device__ __forceinline__ void store_stream(real *base, unsigned byte_off, real v) {
+  __builtin_nontemporal_store(v, (real *)((char *)base + byte_off));
+}
 
 // Projection of the nine Hermite coefficients onto the D2Q9 populations:
 // f_i = w_i [A0 + c.A/cs2 + H2:A2/(2 cs2^2) + (Hxxy Axxy + Hyyx Ayyx)/(2 cs2^3)
@@ -166,22 +179,39 @@ __device__ __forceinline__ real muscl_term(real u, real sm2, real sm1, real s0, 
 
 // --------------------------------------------------------------- the step
 //
-// One workgroup owns a strip of `ow = BW - 4` output columns and `rows` output
-// rows.  Thread t handles virtual column x0 - 2 + t and sweeps the rows of the
-// strip; per row j of the sweep:
-//   A(j)    loads the ten planes at row j (prefetched one row ahead) and puts
-//           u, theta, Gamma and s of the node into LDS rings;
-//   B(j-1)  builds gradients, E, a1 and the nine post-collision populations of
-//           row j-1 (radius-1 stencil through the rings) into an LDS ring;
-//   C(j-2)  pull-streams the populations of row j-2 out of that ring and
-//           updates its entropy (radius-2 stencil), storing both.
-// Each node's moments and collision are therefore computed once per step
-// (plus a 4-column halo), and HBM sees one read and one write of the state.
-template <int BW>
-__global__ __launch_bounds__(BW) void k_step(StepArgs a) {
-  constexpr int R = 6;   // rows kept of the moment rings (C reads rows j-4..j)
-  __shared__ real r_ux[R][BW], r_uy[R][BW], r_th[R][BW], r_gx[R][BW], r_gy[R][BW], r_s[R][BW];
-  __shared__ real r_f[3][kQ][BW];
+// One workgroup owns a tile of CW output columns (x0 a multiple of CW, so
+// every row segment it stores is aligned) and `rows` output rows, plus a
+// radius-2 halo.  Lanes 0..CW-1 handle the tile's columns; an extra wave
+// holds the four halo columns (x0-2, x0-1, x0+CW, x0+CW+1) on its first four
+// lanes.  In the LDS rings a column sits at position ri = column - (x0 - 2).
+// Each lane sweeps the rows of the strip through three stages:
+//   A(j)    moments of row j from the ten planes: u, theta, Gamma and s go
+//           into LDS rings, rho and Pi stay in registers;
+//   B(k)    gradients, E, a1 and the nine post-collision populations of row
+//           k (radius-1 stencil through the rings) into an LDS ring;
+//   C(k)    pull streaming of row k out of that ring and its entropy update
+//           (radius-2 stencil), storing both.
+// Iteration i issues the loads of row i+1, runs B(i-1), a barrier, C(i-2),
+// then A(i+1) on the loads issued at its top, and a second barrier.  Loads are
+// thus consumed in the iteration that issued them, after the B and C work
+// that hides their latency.  Each node's moments and collision are computed
+// once per step (plus a 4-column halo); HBM sees one read and one write of
+// the state.
+//
+// Ring depths are the smallest the two barriers per iteration allow (only a
+// write of A(i+1) may overlap a read of C(i-2) of another wave):
+//   u_x, u_y, Gamma_y: 3 rows (B reads rows k-1..k+1);  Gamma_x: 2 (row k);
+//   theta: 5 (C reads rows k-1 and k+1);  s: 6 (C reads rows k-2..k+2);
+//   post-collision populations by the row they stream from: c_y = 0 -> 2,
+//   c_y = +1 (read one row later) -> 3, c_y = -1 (read in the same row) -> 1.
+template <int CW>
+__global__ __launch_bounds__(CW + 64) void k_step(StepArgs a) {
+  constexpr int W = CW + 4;  // ring width: tile plus halo
+  __shared__ real r_ux[3][W], r_uy[3][W], r_gy[3][W], r_gx[2][W];
+  __shared__ real r_th[5][W], r_s[6][W];
+  __shared__ real r_f0[2][3][W];  // populations 0, 1, 3   (c_y =  0)
+  __shared__ real r_fp[3][3][W];  // populations 2, 5, 6   (c_y = +1)
+  __shared__ real r_fm[3][W];     // populations 4, 7, 8   (c_y = -1)
 
   const DomainArgs &d = a.d;
   const int t = threadIdx.x;
@@ -196,96 +226,114 @@ __global__ __launch_bounds__(BW) void k_step(StepArgs a) {
     bid = xcd < full ? xcd * per + k : full * per + (xcd - full) * (per - 1) + k;
   }
   const int bx = bid % a.nbx, by = bid / a.nbx;
-  const int x0 = bx * a.ow, y0 = by * a.rows;
-  const int vx = x0 - 2 + t;
+  const int x0 = bx * CW, y0 = by * a.rows;
+  // lane -> ring position: tile lanes at 2..CW+1, halo lanes at 0, 1, CW+2, CW+3
+  const int h = t - CW;
+  const int ri = t < CW ? t + 2 : (h < 2 ? h : (h < 4 ? CW + h : 0));
+  const bool a_lane = t < CW + 4;                        // loads and moments
+  const bool b_col = t < CW || h == 1 || h == 2;         // collision: ring 1..CW+2
+  const int vx = x0 - 2 + ri;
   const int cx = map_index(vx, d.nx, d.bcx);
   const int nrow = min(a.rows, d.ny - y0);
   const int nit = nrow + 4;
-  const long long P = d.plane;
-  const bool own_col = (t >= 2) && (t < BW - 2) && (vx < d.nx);
-  const bool b_col = (t >= 1) && (t < BW - 1);
+  const bool own_col = t < CW && vx < d.nx;
   const real cs2 = real(kCs2);
   const real cref = cs2 * (d.theta_ref - real(1));
-
-  // prefetch row 0
-  real ld[kPlanes];
-  {
-    const int ry = map_index(y0 - 2, d.ny, d.bcy);
-    const real *p = a.src + (long long)ry * d.nx + cx;
-#pragma unroll
-    for (int q = 0; q < kPlanes; ++q) ld[q] = p[q * P];
-  }
-
-  // A -> B carry (node state of the row last loaded)
-  real nA_dr = 0, nA_rho = 1, nA_pxx = 0, nA_pyy = 0, nA_pxy = 0, nA_ux = 0, nA_uy = 0, nA_th = 1;
-  // B -> C carry
-  real nB_ux = 0, nB_uy = 0, nB_rho = 1, nB_th = 1, nB_phi = 0;
+  constexpr unsigned kEl = sizeof(real);
   unsigned bad = 0;
 
-  for (int j = 0; j < nit; ++j) {
-    const real cA_dr = nA_dr, cA_rho = nA_rho, cA_pxx = nA_pxx, cA_pyy = nA_pyy,
-               cA_pxy = nA_pxy, cA_ux = nA_ux, cA_uy = nA_uy, cA_th = nA_th;
-    const real cB_ux = nB_ux, cB_uy = nB_uy, cB_rho = nB_rho, cB_th = nB_th, cB_phi = nB_phi;
+  // 32-bit byte offset of virtual row j (x fastest) from the plane bases.
+  auto row_off = [&](int j) {
+    return (unsigned)(map_index(y0 - 2 + j, d.ny, d.bcy) * d.nx + cx) * kEl;
+  };
 
-    // ---------------- A(j): moments of row j
-    {
-      real F[kQ];
+  // Node state of rows k (s0_*) and k+1 (s1_*) carried from A to B.
+  real s0_dr = 0, s0_rho = 1, s0_pxx = 0, s0_pyy = 0, s0_pxy = 0, s0_ux = 0, s0_uy = 0, s0_th = 1;
+  real s1_dr = 0, s1_rho = 1, s1_pxx = 0, s1_pyy = 0, s1_pxy = 0, s1_ux = 0, s1_uy = 0, s1_th = 1;
+  // B -> C carry: B(k) fills nB_*, copied to cB_* at the end of the
+  // iteration, read by C(k) in the next one.
+  real nB_ux = 0, nB_uy = 0, nB_rho = 1, nB_th = 1, nB_phi = 0;
+  real cB_ux = 0, cB_uy = 0, cB_rho = 1, cB_th = 1, cB_phi = 0;
+
+  // A(j): moments of one row from its ten loaded planes.
+  auto stage_a = [&](const int j, const real (&ld)[kPlanes]) {
+    real F[kQ];
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) F[q] = ld[q];
-      const real sv = ld[9];
-      if (j + 1 < nit) {
-        const int ry = map_index(y0 - 1 + j, d.ny, d.bcy);
-        const real *p = a.src + (long long)ry * d.nx + cx;
+    for (int q = 0; q < kQ; ++q) F[q] = ld[q];
+    const real sv = ld[9];
+    const NodeMoments m = node_moments(F, d);
+    const real inv_rho = rcp_fast(m.rho);
+    const real ux = m.jx * inv_rho, uy = m.jy * inv_rho;
+    const real th = node_theta(m.rho, sv, d);
+    r_ux[j % 3][ri] = ux;
+    r_uy[j % 3][ri] = uy;
+    r_th[j % 5][ri] = th;
+    r_gx[j & 1][ri] = m.rho * ux * ((real(1) - th) - ux * ux);
+    r_gy[j % 3][ri] = m.rho * uy * ((real(1) - th) - uy * uy);
+    r_s[j % 6][ri] = sv;
+    s0_dr = s1_dr;
+    s0_rho = s1_rho;
+    s0_pxx = s1_pxx;
+    s0_pyy = s1_pyy;
+    s0_pxy = s1_pxy;
+    s0_ux = s1_ux;
+    s0_uy = s1_uy;
+    s0_th = s1_th;
+    s1_dr = m.dr;
+    s1_rho = m.rho;
+    s1_pxx = m.pxx;
+    s1_pyy = m.pyy;
+    s1_pxy = m.pxy;
+    s1_ux = ux;
+    s1_uy = uy;
+    s1_th = th;
+    bad |= (m.rho > real(0) && th > real(0) && __builtin_isfinite(ux + uy + th)) ? 0u : 1u;
+  };
+
+  if (a_lane) {  // prologue: A(0)
+    real ld[kPlanes];
+    const unsigned off = row_off(0);
 #pragma unroll
-        for (int q = 0; q < kPlanes; ++q) ld[q] = p[q * P];
-      }
-      const NodeMoments m = node_moments(F, d);
-      const real inv_rho = rcp_fast(m.rho);
-      const real ux = m.jx * inv_rho, uy = m.jy * inv_rho;
-      const real th = node_theta(m.rho, sv, d);
-      const int sl = j % R;
-      r_ux[sl][t] = ux;
-      r_uy[sl][t] = uy;
-      r_th[sl][t] = th;
-      r_gx[sl][t] = m.rho * ux * ((real(1) - th) - ux * ux);
-      r_gy[sl][t] = m.rho * uy * ((real(1) - th) - uy * uy);
-      r_s[sl][t] = sv;
-      nA_dr = m.dr;
-      nA_rho = m.rho;
-      nA_pxx = m.pxx;
-      nA_pyy = m.pyy;
-      nA_pxy = m.pxy;
-      nA_ux = ux;
-      nA_uy = uy;
-      nA_th = th;
-      bad |= (m.rho > real(0) && th > real(0) && __builtin_isfinite(ux + uy + th)) ? 0u : 1u;
+    for (int q = 0; q < kPlanes; ++q) ld[q] = load_at(a.src[q], off);
+    stage_a(0, ld);
+  }
+  __syncthreads();
+
+  for (int i = 0; i < nit; ++i) {
+    // ---------------- issue the loads of row i+1 (consumed by A at the end)
+    real ld[kPlanes];
+    const bool do_a = a_lane && i + 1 < nit;
+    if (do_a) {
+      const unsigned off = row_off(i + 1);
+#pragma unroll
+      for (int q = 0; q < kPlanes; ++q) ld[q] = load_at(a.src[q], off);
     }
-    __syncthreads();
+    // A(i) has run for rows 0..i; s1_* holds row i, s0_* row i-1.
 
-    // ---------------- B(j-1): collision of row k = j-1
-    if (j >= 2) {
-      const int k = j - 1;
-      const int sc = k % R, sn = (k + 1) % R, ss = (k + R - 1) % R;
+    // ---------------- B(k), k = i-1: collision
+    if (i >= 2) {
+      const int k = i - 1;
+      const int sc = k % 3, sn = (k + 1) % 3, ss = (k + 2) % 3;
       if (b_col) {
-        const real rho = cA_rho, ux = cA_ux, uy = cA_uy, th = cA_th;
-        const real uxe = r_ux[sc][t + 1], uxw = r_ux[sc][t - 1];
-        const real uye = r_uy[sc][t + 1], uyw = r_uy[sc][t - 1];
-        const real uxn = r_ux[sn][t], uxs = r_ux[ss][t];
-        const real uyn = r_uy[sn][t], uys = r_uy[ss][t];
+        const real rho = s0_rho, ux = s0_ux, uy = s0_uy, th = s0_th;
+        const real uxe = r_ux[sc][ri + 1], uxw = r_ux[sc][ri - 1];
+        const real uye = r_uy[sc][ri + 1], uyw = r_uy[sc][ri - 1];
+        const real uxn = r_ux[sn][ri], uxs = r_ux[ss][ri];
+        const real uyn = r_uy[sn][ri], uys = r_uy[ss][ri];
         const real dxux = real(0.5) * (uxe - uxw), dxuy = real(0.5) * (uye - uyw);
         const real dyux = real(0.5) * (uxn - uxs), dyuy = real(0.5) * (uyn - uys);
         const real div = dxux + dyuy;
         const real p = rho * cs2 * th;
         const real dth = th - d.theta_ref;
-        const real dp = cs2 * (cA_dr * th + d.rho_ref * dth);  // p - p_ref
+        const real dp = cs2 * (s0_dr * th + d.rho_ref * dth);  // p - p_ref
         const real tau = div_fast(d.mu, p);
         const real taub = tau + real(0.5);
         const real itaub = rcp_fast(taub);
-        // E1 (upwind in the sign of the node velocity; centred when u = 0)
-        const real gc = r_gx[sc][t];
-        const real gxe = r_gx[sc][t + 1], gxw = r_gx[sc][t - 1];
-        const real gcy = r_gy[sc][t];
-        const real gyn = r_gy[sn][t], gys = r_gy[ss][t];
+        // E1 (upwind in the sign of the node velocity; centred inside the band)
+        const real gc = r_gx[k & 1][ri];
+        const real gxe = r_gx[k & 1][ri + 1], gxw = r_gx[k & 1][ri - 1];
+        const real gcy = r_gy[sc][ri];
+        const real gyn = r_gy[sn][ri], gys = r_gy[ss][ri];
         real e1x, e1y;
         if (d.flags & kFlagE1Centred) {
           e1x = real(0.5) * (gxe - gxw);
@@ -300,9 +348,9 @@ __global__ __launch_bounds__(BW) void k_step(StepArgs a) {
         // HRR stress
         const real rux = rho * ux, ruy = rho * uy;
         const real ruxx = rux * ux, ruyy = ruy * uy, ruxy = rux * uy;
-        const real prxx = (cA_pxx - dp) - ruxx + real(0.5) * Exx;
-        const real pryy = (cA_pyy - dp) - ruyy + real(0.5) * Eyy;
-        const real prxy = cA_pxy - ruxy;
+        const real prxx = (s0_pxx - dp) - ruxx + real(0.5) * Exx;
+        const real pryy = (s0_pyy - dp) - ruyy + real(0.5) * Eyy;
+        const real prxy = s0_pxy - ruxy;
         const real tp = taub * p;
         const real fdxx = -tp * (dxux - dyuy);
         const real fdxy = -tp * (dyux + dxuy);
@@ -317,9 +365,9 @@ __global__ __launch_bounds__(BW) void k_step(StepArgs a) {
                             (c - uy * uy) * a1xx - real(4) * ux * uy * a1xy;
         const real om = real(1) - itaub;
         // rho c - rho_ref c_ref and rho c^2 - rho_ref c_ref^2 as deviations
-        const real drc = dp - cs2 * cA_dr;
+        const real drc = dp - cs2 * s0_dr;
         const real dc = cs2 * dth;
-        const real drc2 = cA_dr * c * c + d.rho_ref * dc * (c + cref);
+        const real drc2 = s0_dr * c * c + d.rho_ref * dc * (c + cref);
         const real Axx = ruxx + drc + om * a1xx + real(0.5) * Exx;
         const real Ayy = ruyy + drc + om * a1yy + real(0.5) * Eyy;
         const real Axy = ruxy + om * a1xy;
@@ -328,14 +376,20 @@ __global__ __launch_bounds__(BW) void k_step(StepArgs a) {
         const real Axyy = ruyy * ux + rc * ux + om * a1xyy;
         const real Axxyy = ruxx * uy * uy + rc * (ux * ux + uy * uy) + drc2 + om * a1xxyy;
         real f[kQ];
-        project(cA_dr, rux, ruy, Axx, Axy, Ayy, Axxy, Axyy, Axxyy, f);
-        const int fs = k % 3;
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) r_f[fs][q][t] = f[q];
+        project(s0_dr, rux, ruy, Axx, Axy, Ayy, Axxy, Axyy, Axxyy, f);
+        r_f0[k & 1][0][ri] = f[0];
+        r_f0[k & 1][1][ri] = f[1];
+        r_f0[k & 1][2][ri] = f[3];
+        r_fp[sc][0][ri] = f[2];
+        r_fp[sc][1][ri] = f[5];
+        r_fp[sc][2][ri] = f[6];
+        r_fm[0][ri] = f[4];
+        r_fm[1][ri] = f[7];
+        r_fm[2][ri] = f[8];
         real phi;
         if (d.flags & kFlagPhiFD) {
-          const real a = dxux - dyuy, b = dyux + dxuy;
-          phi = d.mu * (a * a + b * b);
+          const real aa = dxux - dyuy, bb = dyux + dxuy;
+          phi = d.mu * (aa * aa + bb * bb);
         } else {
           phi = -(tau * itaub) * (a1xx * dxux + a1xy * (dyux + dxuy) + a1yy * dyuy);
         }
@@ -348,37 +402,44 @@ __global__ __launch_bounds__(BW) void k_step(StepArgs a) {
     }
     __syncthreads();
 
-    // ---------------- C(j-2): stream and entropy of row k = j-2
-    if (j >= 4) {
-      const int k = j - 2;
-      if (own_col) {
-        const int f0 = k % 3, fm = (k + 2) % 3, fp = (k + 1) % 3;  // rows k, k-1, k+1
-        real Fo[kQ];
-        Fo[0] = r_f[f0][0][t];
-        Fo[1] = r_f[f0][1][t - 1];
-        Fo[2] = r_f[fm][2][t];
-        Fo[3] = r_f[f0][3][t + 1];
-        Fo[4] = r_f[fp][4][t];
-        Fo[5] = r_f[fm][5][t - 1];
-        Fo[6] = r_f[fm][6][t + 1];
-        Fo[7] = r_f[fp][7][t + 1];
-        Fo[8] = r_f[fp][8][t - 1];
-        const int s0 = k % R, s1 = (k + 1) % R, s2 = (k + 2) % R, sm1 = (k + R - 1) % R,
-                  sm2 = (k + R - 2) % R;
-        const real sc = r_s[s0][t];
-        const real advx = muscl_term(cB_ux, r_s[s0][t - 2], r_s[s0][t - 1], sc, r_s[s0][t + 1],
-                                     r_s[s0][t + 2]);
-        const real advy = muscl_term(cB_uy, r_s[sm2][t], r_s[sm1][t], sc, r_s[s1][t], r_s[s2][t]);
-        const real lap = ((r_th[s0][t + 1] + r_th[s0][t - 1]) + (r_th[s1][t] + r_th[sm1][t])) -
-                         real(4) * cB_th;
-        const real snew = sc - (advx + advy) + div_fast(d.lambda * lap + cB_phi, cB_rho * cB_th);
-        const int oy = y0 + k - 2;
-        real *o = a.dst + (long long)oy * d.nx + vx;
+    // ---------------- C(k), k = i-2: stream and entropy
+    if (i >= 4 && own_col) {
+      const int k = i - 2;
+      const int z = k & 1, pm = (k + 2) % 3;  // slot of row k in r_f0, of row k-1 in r_fp
+      real Fo[kQ];
+      Fo[0] = r_f0[z][0][ri];
+      Fo[1] = r_f0[z][1][ri - 1];
+      Fo[3] = r_f0[z][2][ri + 1];
+      Fo[2] = r_fp[pm][0][ri];
+      Fo[5] = r_fp[pm][1][ri - 1];
+      Fo[6] = r_fp[pm][2][ri + 1];
+      Fo[4] = r_fm[0][ri];
+      Fo[7] = r_fm[1][ri + 1];
+      Fo[8] = r_fm[2][ri - 1];
+      const int s0 = k % 6, s1 = (k + 1) % 6, s2 = (k + 2) % 6, sm1 = (k + 5) % 6,
+                sm2 = (k + 4) % 6;
+      const real sc = r_s[s0][ri];
+      const real advx = muscl_term(cB_ux, r_s[s0][ri - 2], r_s[s0][ri - 1], sc, r_s[s0][ri + 1],
+                                   r_s[s0][ri + 2]);
+      const real advy = muscl_term(cB_uy, r_s[sm2][ri], r_s[sm1][ri], sc, r_s[s1][ri], r_s[s2][ri]);
+      const int t0 = k % 5, tn = (k + 1) % 5, ts = (k + 4) % 5;
+      const real lap = ((r_th[t0][ri + 1] + r_th[t0][ri - 1]) + (r_th[tn][ri] + r_th[ts][ri])) -
+                       real(4) * cB_th;
+      const real snew = sc - (advx + advy) + div_fast(d.lambda * lap + cB_phi, cB_rho * cB_th);
+      const unsigned off = (unsigned)((y0 + k - 2) * d.nx + vx) * kEl;
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) o[q * P] = Fo[q];
-        o[9 * P] = snew;
-      }
+      for (int q = 0; q < kQ; ++q) store_stream(a.dst[q], off, Fo[q]);
+      store_stream(a.dst[9], off, snew);
     }
+    cB_ux = nB_ux;
+    cB_uy = nB_uy;
+    cB_rho = nB_rho;
+    cB_th = nB_th;
+    cB_phi = nB_phi;
+
+    // ---------------- A(i+1) on the loads issued at the top
+    if (do_a) stage_a(i + 1, ld);
+    __syncthreads();
   }
   if (bad) atomicOr(a.status, 1u);
 }

@@ -40,24 +40,25 @@ hipError_t step(const HostDomain &h, const void *src, void *dst, unsigned *statu
                 const TileShape &tile, hipStream_t st) {
   StepArgs a;
   a.d = to_device(h);
-  a.src = (const real *)src;
-  a.dst = (real *)dst;
+  for (int q = 0; q < kPlanes; ++q) {
+    a.src[q] = (const real *)src + (long long)q * h.plane;
+    a.dst[q] = (real *)dst + (long long)q * h.plane;
+  }
   a.status = status;
   a.rows = tile.rows;
-  a.ow = tile.bw - 4;
-  a.nbx = (h.nx + a.ow - 1) / a.ow;
+  a.nbx = (h.nx + tile.bw - 1) / tile.bw;
   a.nby = (h.ny + tile.rows - 1) / tile.rows;
   a.xcd_remap = tile.xcd_remap;
   const int nblk = a.nbx * a.nby;
   switch (tile.bw) {
   case 64:
-    hipLaunchKernelGGL(k_step<64>, dim3(nblk), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_step<64>, dim3(nblk), dim3(64 + 64), 0, st, a);
     break;
   case 128:
-    hipLaunchKernelGGL(k_step<128>, dim3(nblk), dim3(128), 0, st, a);
+    hipLaunchKernelGGL(k_step<128>, dim3(nblk), dim3(128 + 64), 0, st, a);
     break;
   case 256:
-    hipLaunchKernelGGL(k_step<256>, dim3(nblk), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_step<256>, dim3(nblk), dim3(256 + 64), 0, st, a);
     break;
   default:
     return hipErrorInvalidValue;

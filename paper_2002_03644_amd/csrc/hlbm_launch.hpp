@@ -17,7 +17,7 @@ struct HostDomain {
 };
 
 struct TileShape {
-  int bw;        // threads per workgroup: 64, 128 or 256
+  int bw;        // tile width in columns (64, 128 or 256); workgroup = bw + 64 lanes
   int rows;      // output rows per strip
   int xcd_remap; // 0 or 1
 };
