@@ -159,6 +159,61 @@ const char *hlbm_strerror(int code);
 int hlbm_entropy_from_theta(int32_t dtype, double gamma, const void *rho, const void *theta,
                             void *s, int64_t n, hlbm_stream_t stream);
 
+
+/* ------------------------------------------------------------------------
+ * Batched domains: many independent domains (each with its own hlbm_params,
+ * all of one dtype) advanced together.  One step is ONE launch of a
+ * persistent kernel whose workgroups walk a list of (domain, tile) items,
+ * largest domains first; with use_graph the launches are replayed from a
+ * captured hipGraph.  Fields of all domains are concatenated: domain k's
+ * [ny_k][nx_k] block starts at element sum_{j<k} nx_j ny_j.  Each domain has
+ * its own divergence flag; a diverged domain is frozen (its tiles are
+ * skipped) while the others continue.
+ * ------------------------------------------------------------------------ */
+typedef struct hlbm_batch hlbm_batch;
+
+/* Workspace bytes for `count` domains, or 0 if any parameter set is invalid
+ * or the dtypes differ.  Host-only. */
+size_t hlbm_batch_workspace_bytes(const hlbm_params *params, int32_t count);
+
+/* Initialise every domain as hlbm_init does.  params: host array of `count`;
+ * rho, ux, uy, s: concatenated device fields.  Synchronises `stream`. */
+int hlbm_batch_init(hlbm_batch **out, const hlbm_params *params, int32_t count, void *workspace,
+                    size_t ws_bytes, const void *rho, const void *ux, const void *uy,
+                    const void *s, hlbm_stream_t stream);
+
+/* Enqueue nsteps steps of all domains.  use_graph = 1 captures a two-step
+ * hipGraph on first use (stream must not be NULL) and replays it. */
+int hlbm_batch_step(hlbm_batch *b, int32_t nsteps, int32_t use_graph, hlbm_stream_t stream);
+
+/* Concatenated macroscopic fields of all domains (NULL outputs skipped). */
+int hlbm_batch_moments(hlbm_batch *b, void *rho, void *ux, void *uy, void *s, void *theta,
+                       hlbm_stream_t stream);
+
+/* Per-domain divergence flags (host_flags may be NULL); returns the number of
+ * diverged domains (>= 0) or an error.  Synchronises `stream`. */
+int hlbm_batch_status(hlbm_batch *b, int32_t *host_flags, hlbm_stream_t stream);
+
+/* Tile shape of the batched kernel: tile_w in {64, 128, 256}, tile_h >= 8.
+ * Synchronises `stream`. */
+int hlbm_batch_set_tile(hlbm_batch *b, int32_t tile_w, int32_t tile_h, hlbm_stream_t stream);
+
+/* Time `steps` steps for every tile shape in {64, 128, 256} x {16, 32, 64,
+ * 128}, keep the fastest and report it.  Advances the domains; save and load
+ * the state around it to keep them.  Synchronises `stream`. */
+int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, int32_t *host_best_w, int32_t *host_best_h,
+                        hlbm_stream_t stream);
+
+/* Raw state of all domains (for checkpoint, or around hlbm_batch_autotune);
+ * load also clears the divergence flags. */
+size_t hlbm_batch_state_bytes(const hlbm_batch *b);
+int hlbm_batch_save_state(hlbm_batch *b, void *dst, hlbm_stream_t stream);
+int hlbm_batch_load_state(hlbm_batch *b, const void *src, hlbm_stream_t stream);
+
+int64_t hlbm_batch_nodes(const hlbm_batch *b);       /* sum of nx ny */
+int64_t hlbm_batch_steps_done(const hlbm_batch *b);
+void hlbm_batch_destroy(hlbm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,10 +4,10 @@ The compute path is libhlbm.so (HIP kernels behind the C ABI of
 include/hlbm.h); this package only marshals arguments.  Build the library
 with ``python -m paper_2002_03644_amd.build``.
 """
-from ._lib import (F32, F64, HLBM_EDIVERGED, HLBM_EINVAL, HLBM_EWORKSPACE, HLBM_OK,
+from ._lib import (F32, F64, BatchSolver, HLBM_EDIVERGED, HLBM_EINVAL, HLBM_EWORKSPACE, HLBM_OK,
                    HLBM_WARN_CFL, HlbmError, Params, Solver, entropy_from_theta, lib,
                    strerror, validate, workspace_bytes)
 
-__all__ = ["Params", "Solver", "HlbmError", "entropy_from_theta", "lib", "strerror",
+__all__ = ["Params", "Solver", "BatchSolver", "HlbmError", "entropy_from_theta", "lib", "strerror",
            "validate", "workspace_bytes", "F32", "F64", "HLBM_OK", "HLBM_WARN_CFL",
            "HLBM_EINVAL", "HLBM_EWORKSPACE", "HLBM_EDIVERGED"]

@@ -71,6 +71,21 @@ def lib():
             "hlbm_destroy": (None, [vp]),
             "hlbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "hlbm_entropy_from_theta": (ctypes.c_int, [i32, ctypes.c_double, vp, vp, vp, i64, vp]),
+            "hlbm_batch_workspace_bytes": (sz, [PP, i32]),
+            "hlbm_batch_init": (ctypes.c_int, [ctypes.POINTER(vp), PP, i32, vp, sz, vp, vp, vp, vp,
+                                               vp]),
+            "hlbm_batch_step": (ctypes.c_int, [vp, i32, i32, vp]),
+            "hlbm_batch_moments": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+            "hlbm_batch_status": (ctypes.c_int, [vp, ctypes.POINTER(i32), vp]),
+            "hlbm_batch_set_tile": (ctypes.c_int, [vp, i32, i32, vp]),
+            "hlbm_batch_autotune": (ctypes.c_int, [vp, i32, ctypes.POINTER(i32),
+                                                   ctypes.POINTER(i32), vp]),
+            "hlbm_batch_state_bytes": (sz, [vp]),
+            "hlbm_batch_save_state": (ctypes.c_int, [vp, vp, vp]),
+            "hlbm_batch_load_state": (ctypes.c_int, [vp, vp, vp]),
+            "hlbm_batch_nodes": (i64, [vp]),
+            "hlbm_batch_steps_done": (i64, [vp]),
+            "hlbm_batch_destroy": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -253,3 +268,150 @@ class Solver:
 
     def load_state(self, buf):
         _check(lib().hlbm_load_state(self.h, _ptr(buf), _stream()), "hlbm_load_state")
+
+
+class BatchSolver:
+    """Many independent domains advanced by one persistent launch per step.
+
+    ``params``: list of Params (one dtype); ``fields``: list of (rho, ux, uy,
+    theta) per domain (host or device arrays).  Graph replay needs a
+    non-default stream, so the solver owns one and orders it after the
+    caller's current stream."""
+
+    def __init__(self, params, fields, device="cuda"):
+        import torch
+        if len(params) != len(fields) or not params:
+            raise ValueError("one field tuple per parameter set")
+        self.params = list(params)
+        self.device = torch.device(device)
+        td = self.params[0].torch_dtype
+        self.sizes = [p.nx * p.ny for p in self.params]
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        n = int(self.offsets[-1])
+        cat = [torch.empty(n, dtype=td, device=self.device) for _ in range(3)]
+        s_all = torch.empty(n, dtype=td, device=self.device)
+        for k, (p, f) in enumerate(zip(self.params, fields)):
+            a, b = int(self.offsets[k]), int(self.offsets[k + 1])
+            rho = _dev_field(f[0], p, self.device).reshape(-1)
+            cat[0][a:b] = rho
+            cat[1][a:b] = _dev_field(f[1], p, self.device).reshape(-1)
+            cat[2][a:b] = _dev_field(f[2], p, self.device).reshape(-1)
+            th = _dev_field(f[3], p, self.device).reshape(-1)
+            s_all[a:b] = entropy_from_theta(rho, th, p.gamma, p.dtype, self.device)
+        arr = (CParams * len(self.params))(*[p.c() for p in self.params])
+        self._carr = arr
+        nbytes = lib().hlbm_batch_workspace_bytes(arr, len(self.params))
+        if nbytes == 0:
+            raise HlbmError(HLBM_EINVAL, "hlbm_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(device=self.device)  # default priority
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        h = ctypes.c_void_p()
+        _check(lib().hlbm_batch_init(ctypes.byref(h), arr, len(self.params), _ptr(self.workspace),
+                                     nbytes, _ptr(cat[0]), _ptr(cat[1]), _ptr(cat[2]),
+                                     _ptr(s_all), _stream(self.stream)), "hlbm_batch_init")
+        self.h = h
+        self.nodes = int(lib().hlbm_batch_nodes(h))
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().hlbm_batch_destroy(h)
+            self.h = None
+
+    @property
+    def steps(self):
+        return int(lib().hlbm_batch_steps_done(self.h))
+
+    def _enter(self):
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        import torch
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def step(self, n=1, graph=True):
+        self._enter()
+        _check(lib().hlbm_batch_step(self.h, int(n), int(bool(graph)), _stream(self.stream)),
+               "hlbm_batch_step")
+        self._leave()
+        return self
+
+    def moments(self):
+        """List of per-domain dicts of [ny][nx] tensors (views of one buffer)."""
+        import torch
+        td = self.params[0].torch_dtype
+        n = int(self.offsets[-1])
+        cat = {k: torch.empty(n, dtype=td, device=self.device)
+               for k in ("rho", "ux", "uy", "s", "theta")}
+        self._enter()
+        _check(lib().hlbm_batch_moments(self.h, _ptr(cat["rho"]), _ptr(cat["ux"]),
+                                        _ptr(cat["uy"]), _ptr(cat["s"]), _ptr(cat["theta"]),
+                                        _stream(self.stream)), "hlbm_batch_moments")
+        self._leave()
+        out = []
+        for k, p in enumerate(self.params):
+            a, b = int(self.offsets[k]), int(self.offsets[k + 1])
+            out.append({key: v[a:b].view(p.ny, p.nx) for key, v in cat.items()})
+        return out
+
+    def status(self):
+        flags = (ctypes.c_int32 * len(self.params))()
+        self._enter()
+        bad = _check(lib().hlbm_batch_status(self.h, flags, _stream(self.stream)),
+                     "hlbm_batch_status")
+        return bad, np.array(flags[:], dtype=np.int32)
+
+    def set_tile(self, tile_w, tile_h):
+        self._enter()
+        _check(lib().hlbm_batch_set_tile(self.h, int(tile_w), int(tile_h), _stream(self.stream)),
+               "hlbm_batch_set_tile")
+
+    def save_state(self):
+        import torch
+        buf = torch.empty(lib().hlbm_batch_state_bytes(self.h), dtype=torch.uint8,
+                          device=self.device)
+        self._enter()
+        _check(lib().hlbm_batch_save_state(self.h, _ptr(buf), _stream(self.stream)),
+               "hlbm_batch_save_state")
+        self._leave()
+        return buf
+
+    def load_state(self, buf):
+        self._enter()
+        _check(lib().hlbm_batch_load_state(self.h, _ptr(buf), _stream(self.stream)),
+               "hlbm_batch_load_state")
+        self._leave()
+
+    def signature(self):
+        import hashlib
+        key = ";".join(f"{p.nx}x{p.ny}:{p.dtype}" for p in self.params)
+        return hashlib.sha256(key.encode()).hexdigest()[:20]
+
+    def autotune(self, steps=3, cache_path=None):
+        """Pick the fastest tile shape by timing (state restored afterwards).
+        With ``cache_path`` the choice is read from / written to a JSON file
+        keyed by the batch's domain sizes and dtype."""
+        import json
+        sig = self.signature()
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                cache = json.load(fh)
+            if sig in cache:
+                w, h = cache[sig]
+                self.set_tile(w, h)
+                return int(w), int(h)
+        snap = self.save_state()
+        bw, bh = ctypes.c_int32(0), ctypes.c_int32(0)
+        self._enter()
+        _check(lib().hlbm_batch_autotune(self.h, int(steps), ctypes.byref(bw), ctypes.byref(bh),
+                                         _stream(self.stream)), "hlbm_batch_autotune")
+        self.load_state(snap)
+        if cache_path:
+            cache[sig] = [bw.value, bh.value]
+            os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
+            with open(cache_path, "w") as fh:
+                json.dump(cache, fh, indent=1)
+        return bw.value, bh.value

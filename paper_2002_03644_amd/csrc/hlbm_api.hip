@@ -5,6 +5,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <new>
+#include <vector>
+
 #include <hip/hip_runtime.h>
 
 #include "hlbm.h"
@@ -328,6 +332,362 @@ int hlbm_entropy_from_theta(int32_t dtype, double gamma, const void *rho, const 
   hipError_t e = dtype == HLBM_F64 ? hlbm::f64::entropy(rho, theta, s, n, gamma, st)
                                    : hlbm::f32::entropy(rho, theta, s, n, gamma, st);
   return hip_status(e);
+}
+
+}  // extern "C"
+
+// ======================================================================
+// Batched domains
+// ======================================================================
+
+struct hlbm_batch {
+  int count = 0, dtype = 0;
+  std::vector<hlbm_params> params;
+  std::vector<hlbm::HostDomain> doms;
+  std::vector<long long> offs;        // element offset of each domain's state in a buffer
+  std::vector<long long> field_offs;  // offset of each domain in the concatenated fields
+  std::vector<long long> state_elems; // ten planes of each domain
+  char *ws = nullptr;
+  size_t off_buf1 = 0, off_doms = 0, off_offs = 0, off_items = 0, off_stat = 0, total = 0;
+  size_t state_bytes = 0;             // one buffer
+  int max_items = 0, nitems = 0, tile_w = 128, tile_h = 32, grid = 1, cur = 0, ncu = 1;
+  int64_t steps = 0, nodes = 0;
+  hipGraphExec_t graph = nullptr;
+  int graph_cur = -1;
+};
+
+namespace {
+
+constexpr int kBatchTileW[3] = {64, 128, 256};
+constexpr int kBatchMinRows = 8;
+
+int batch_items_for(const hlbm_batch *b, int tw, int th, std::vector<int> *out) {
+  // largest domains first: the round-robin walk then ends on small items
+  std::vector<int> order(b->count);
+  for (int k = 0; k < b->count; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (long long)b->params[x].nx * b->params[x].ny >
+           (long long)b->params[y].nx * b->params[y].ny;
+  });
+  int n = 0;
+  for (int k : order) {
+    const int rows = std::min(th, b->params[k].ny);
+    const int nbx = (b->params[k].nx + tw - 1) / tw, nby = (b->params[k].ny + rows - 1) / rows;
+    for (int by = 0; by < nby; ++by)
+      for (int bx = 0; bx < nbx; ++bx) {
+        if (out) {
+          out->push_back(k);
+          out->push_back(bx);
+          out->push_back(by);
+          out->push_back(rows);
+        }
+        ++n;
+      }
+  }
+  return n;
+}
+
+void batch_layout(hlbm_batch *b) {
+  const size_t el = elem_size(b->dtype);
+  long long acc = 0;
+  b->offs.resize(b->count);
+  b->state_elems.resize(b->count);
+  b->field_offs.resize(b->count);
+  long long facc = 0;
+  for (int k = 0; k < b->count; ++k) {
+    b->offs[k] = acc;
+    b->state_elems[k] = plane_elems(&b->params[k]) * 10;
+    acc += b->state_elems[k];
+    b->field_offs[k] = facc;
+    facc += (long long)b->params[k].nx * b->params[k].ny;
+  }
+  b->nodes = facc;
+  b->state_bytes = round_up((size_t)acc * el, kAlign);
+  b->max_items = batch_items_for(b, 64, kBatchMinRows, nullptr);
+  b->off_buf1 = b->state_bytes;
+  b->off_doms = 2 * b->state_bytes;
+  const size_t dbytes = std::max(hlbm::f32::domain_args_bytes(), hlbm::f64::domain_args_bytes());
+  b->off_offs = b->off_doms + round_up(dbytes * b->count, kAlign);
+  b->off_items = b->off_offs + round_up(sizeof(long long) * b->count, kAlign);
+  b->off_stat = b->off_items + round_up(sizeof(int) * 4 * (size_t)b->max_items, kAlign);
+  b->total = b->off_stat + round_up(sizeof(unsigned) * b->count, kAlign);
+}
+
+int batch_validate(const hlbm_params *p, int32_t count) {
+  if (!p || count < 1) return HLBM_EINVAL;
+  for (int k = 0; k < count; ++k) {
+    if (hlbm_validate(&p[k]) != HLBM_OK) return HLBM_EINVAL;
+    if (p[k].dtype != p[0].dtype) return HLBM_EINVAL;
+  }
+  return HLBM_OK;
+}
+
+hipError_t batch_upload_items(hlbm_batch *b, int tw, int th, hipStream_t st) {
+  std::vector<int> items;
+  items.reserve(4 * (size_t)b->max_items);
+  b->nitems = batch_items_for(b, tw, th, &items);
+  if (b->nitems > b->max_items) return hipErrorInvalidValue;
+  hipError_t e = hipMemcpyAsync(b->ws + b->off_items, items.data(), sizeof(int) * items.size(),
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // host vector must outlive the copy
+  if (e != hipSuccess) return e;
+  b->tile_w = tw;
+  b->tile_h = th;
+  const int per_cu = b->dtype == HLBM_F64 ? hlbm::f64::batch_blocks_per_cu(tw)
+                                          : hlbm::f32::batch_blocks_per_cu(tw);
+  b->grid = std::max(1, std::min(b->nitems, per_cu * b->ncu));
+  if (b->graph) {
+    hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  return hipSuccess;
+}
+
+hipError_t batch_launch(hlbm_batch *b, int from, hipStream_t st) {
+  const char *src = b->ws + (from ? b->off_buf1 : 0);
+  char *dst = b->ws + (from ? 0 : b->off_buf1);
+  const long long *offs = (const long long *)(b->ws + b->off_offs);
+  unsigned *stat = (unsigned *)(b->ws + b->off_stat);
+  const void *items = b->ws + b->off_items;
+  const void *doms = b->ws + b->off_doms;
+  // tile_h is carried per item (rows of that domain's strips)
+  if (b->dtype == HLBM_F64)
+    return hlbm::f64::step_batch(doms, offs, items, b->nitems, src, dst, stat, b->tile_h,
+                                 b->tile_w, b->grid, st);
+  return hlbm::f32::step_batch(doms, offs, items, b->nitems, src, dst, stat, b->tile_h,
+                               b->tile_w, b->grid, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hlbm_batch_workspace_bytes(const hlbm_params *params, int32_t count) {
+  if (batch_validate(params, count) != HLBM_OK) return 0;
+  hlbm_batch b;
+  b.count = count;
+  b.dtype = params[0].dtype;
+  b.params.assign(params, params + count);
+  batch_layout(&b);
+  return b.total;
+}
+
+int hlbm_batch_init(hlbm_batch **out, const hlbm_params *params, int32_t count, void *workspace,
+                    size_t ws_bytes, const void *rho, const void *ux, const void *uy,
+                    const void *s, hlbm_stream_t stream) {
+  if (!out) return HLBM_EINVAL;
+  *out = nullptr;
+  if (batch_validate(params, count) != HLBM_OK || !rho || !ux || !uy || !s) return HLBM_EINVAL;
+  hlbm_batch *b = new (std::nothrow) hlbm_batch();
+  if (!b) return HLBM_ENOMEM;
+  b->count = count;
+  b->dtype = params[0].dtype;
+  b->params.assign(params, params + count);
+  batch_layout(b);
+  if (!workspace || ws_bytes < b->total || (uintptr_t)workspace % kAlign) {
+    delete b;
+    return HLBM_EWORKSPACE;
+  }
+  b->ws = (char *)workspace;
+  b->doms.resize(count);
+  for (int k = 0; k < count; ++k) {
+    fill_domain(&b->params[k], &b->doms[k]);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  // domain table and offsets
+  std::vector<char> packed(std::max(hlbm::f32::domain_args_bytes(),
+                                    hlbm::f64::domain_args_bytes()) * count);
+  if (b->dtype == HLBM_F64)
+    hlbm::f64::pack_domains(b->doms.data(), count, packed.data());
+  else
+    hlbm::f32::pack_domains(b->doms.data(), count, packed.data());
+  const size_t dbytes = b->dtype == HLBM_F64 ? hlbm::f64::domain_args_bytes()
+                                             : hlbm::f32::domain_args_bytes();
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->ws + b->off_doms, packed.data(), dbytes * count, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->ws + b->off_offs, b->offs.data(), sizeof(long long) * count,
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_clear_words, dim3((count + 255) / 256), dim3(256), 0, st,
+                       (unsigned *)(b->ws + b->off_stat), count);
+    e = hipGetLastError();
+  }
+  const size_t el = elem_size(b->dtype);
+  for (int k = 0; k < count && e == hipSuccess; ++k) {
+    const long long fo = b->field_offs[k];
+    const char *r = (const char *)rho + fo * el, *u = (const char *)ux + fo * el;
+    const char *v = (const char *)uy + fo * el, *sv = (const char *)s + fo * el;
+    char *dst = b->ws + b->offs[k] * el;
+    e = b->dtype == HLBM_F64 ? hlbm::f64::init(b->doms[k], r, u, v, sv, dst, st)
+                             : hlbm::f32::init(b->doms[k], r, u, v, sv, dst, st);
+  }
+  if (e == hipSuccess) e = batch_upload_items(b, 128, 32, st);  // synchronises
+  if (e != hipSuccess) {
+    delete b;
+    return HLBM_EHIP;
+  }
+  *out = b;
+  return HLBM_OK;
+}
+
+int hlbm_batch_step(hlbm_batch *b, int32_t nsteps, int32_t use_graph, hlbm_stream_t stream) {
+  if (!b || nsteps < 0) return HLBM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (use_graph && !st) return HLBM_EINVAL;  // the legacy null stream cannot be captured
+  int n = nsteps;
+  if (use_graph && n >= 2) {
+    if (!b->graph || b->graph_cur != b->cur) {
+      if (b->graph) {
+        hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return HLBM_EHIP;
+      hipError_t e1 = batch_launch(b, b->cur, st);
+      hipError_t e2 = batch_launch(b, b->cur ^ 1, st);
+      e = hipStreamEndCapture(st, &g);
+      if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return HLBM_EHIP;
+      }
+      e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        b->graph = nullptr;
+        return HLBM_EHIP;
+      }
+      b->graph_cur = b->cur;
+    }
+    for (; n >= 2; n -= 2) {
+      if (hipGraphLaunch(b->graph, st) != hipSuccess) return HLBM_EHIP;
+      b->steps += 2;
+    }
+  }
+  for (; n > 0; --n) {
+    if (batch_launch(b, b->cur, st) != hipSuccess) return HLBM_EHIP;
+    b->cur ^= 1;
+    b->steps++;
+  }
+  return HLBM_OK;
+}
+
+int hlbm_batch_moments(hlbm_batch *b, void *rho, void *ux, void *uy, void *s, void *theta,
+                       hlbm_stream_t stream) {
+  if (!b) return HLBM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t el = elem_size(b->dtype);
+  auto at = [&](void *p, long long fo) { return p ? (void *)((char *)p + fo * el) : nullptr; };
+  for (int k = 0; k < b->count; ++k) {
+    const long long fo = b->field_offs[k];
+    const char *state = b->ws + (b->cur ? b->off_buf1 : 0) + b->offs[k] * el;
+    hipError_t e = b->dtype == HLBM_F64
+                       ? hlbm::f64::moments(b->doms[k], state, at(rho, fo), at(ux, fo), at(uy, fo),
+                                            at(s, fo), at(theta, fo), st)
+                       : hlbm::f32::moments(b->doms[k], state, at(rho, fo), at(ux, fo), at(uy, fo),
+                                            at(s, fo), at(theta, fo), st);
+    if (e != hipSuccess) return HLBM_EHIP;
+  }
+  return HLBM_OK;
+}
+
+int hlbm_batch_status(hlbm_batch *b, int32_t *host_flags, hlbm_stream_t stream) {
+  if (!b) return HLBM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<unsigned> w(b->count);
+  if (hipMemcpyAsync(w.data(), b->ws + b->off_stat, sizeof(unsigned) * b->count,
+                     hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return HLBM_EHIP;
+  int bad = 0;
+  for (int k = 0; k < b->count; ++k) {
+    if (host_flags) host_flags[k] = w[k] ? 1 : 0;
+    bad += w[k] ? 1 : 0;
+  }
+  return bad;
+}
+
+int hlbm_batch_set_tile(hlbm_batch *b, int32_t tile_w, int32_t tile_h, hlbm_stream_t stream) {
+  if (!b) return HLBM_EINVAL;
+  if (tile_w != 64 && tile_w != 128 && tile_w != 256) return HLBM_EINVAL;
+  if (tile_h < kBatchMinRows) return HLBM_EINVAL;
+  return hip_status(batch_upload_items(b, tile_w, tile_h, (hipStream_t)stream));
+}
+
+int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, int32_t *host_best_w, int32_t *host_best_h,
+                        hlbm_stream_t stream) {
+  if (!b || steps < 1) return HLBM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const int hs[4] = {16, 32, 64, 128};
+  float best = 1e30f;
+  int bw = b->tile_w, bh = b->tile_h;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return HLBM_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return HLBM_EHIP;
+  }
+  int rc = HLBM_OK;
+  for (int tw : kBatchTileW) {
+    for (int th : hs) {
+      if (batch_upload_items(b, tw, th, st) != hipSuccess) { rc = HLBM_EHIP; break; }
+      if (hlbm_batch_step(b, 1, 0, st) != HLBM_OK) { rc = HLBM_EHIP; break; }
+      hipEventRecord(e0, st);
+      if (hlbm_batch_step(b, steps, 0, st) != HLBM_OK) { rc = HLBM_EHIP; break; }
+      hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) { rc = HLBM_EHIP; break; }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        bw = tw;
+        bh = th;
+      }
+    }
+    if (rc != HLBM_OK) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != HLBM_OK) return rc;
+  if (batch_upload_items(b, bw, bh, st) != hipSuccess) return HLBM_EHIP;
+  if (host_best_w) *host_best_w = bw;
+  if (host_best_h) *host_best_h = bh;
+  return HLBM_OK;
+}
+
+size_t hlbm_batch_state_bytes(const hlbm_batch *b) { return b ? b->state_bytes : 0; }
+
+int hlbm_batch_save_state(hlbm_batch *b, void *dst, hlbm_stream_t stream) {
+  if (!b || !dst) return HLBM_EINVAL;
+  return hip_status(hipMemcpyAsync(dst, b->ws + (b->cur ? b->off_buf1 : 0), b->state_bytes,
+                                   hipMemcpyDeviceToDevice, (hipStream_t)stream));
+}
+
+int hlbm_batch_load_state(hlbm_batch *b, const void *src, hlbm_stream_t stream) {
+  if (!b || !src) return HLBM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(b->ws + (b->cur ? b->off_buf1 : 0), src, b->state_bytes,
+                                hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_clear_words, dim3((b->count + 255) / 256), dim3(256), 0, st,
+                       (unsigned *)(b->ws + b->off_stat), b->count);
+    e = hipGetLastError();
+  }
+  return hip_status(e);
+}
+
+int64_t hlbm_batch_nodes(const hlbm_batch *b) { return b ? b->nodes : -1; }
+
+int64_t hlbm_batch_steps_done(const hlbm_batch *b) { return b ? b->steps : -1; }
+
+void hlbm_batch_destroy(hlbm_batch *b) {
+  if (!b) return;
+  if (b->graph) hipGraphExecDestroy(b->graph);
+  delete b;
 }
 
 }  // extern "C"

@@ -54,8 +54,8 @@ struct DomainArgs {
 
 struct StepArgs {
   DomainArgs d;
-  const real *src[kPlanes];  // per-plane base pointers (uniform: SGPR operands)
-  real *dst[kPlanes];
+  const real *src;     // plane 0 of the state read this step
+  real *dst;           // plane 0 of the state written
   unsigned *status;    // bit 0 set when a node diverged
   int rows;            // output rows per strip
   int nbx, nby;        // workgroups along x and y
@@ -204,29 +204,42 @@ __device__ __forceinline__ real muscl_term(real u, real sm2, real sm1, real s0, 
 //   theta: 5 (C reads rows k-1 and k+1);  s: 6 (C reads rows k-2..k+2);
 //   post-collision populations by the row they stream from: c_y = 0 -> 2,
 //   c_y = +1 (read one row later) -> 3, c_y = -1 (read in the same row) -> 1.
+// Shared memory of one tile sweep.
 template <int CW>
-__global__ __launch_bounds__(CW + 64) void k_step(StepArgs a) {
-  constexpr int W = CW + 4;  // ring width: tile plus halo
-  __shared__ real r_ux[3][W], r_uy[3][W], r_gy[3][W], r_gx[2][W];
-  __shared__ real r_th[5][W], r_s[6][W];
-  __shared__ real r_f0[2][3][W];  // populations 0, 1, 3   (c_y =  0)
-  __shared__ real r_fp[3][3][W];  // populations 2, 5, 6   (c_y = +1)
-  __shared__ real r_fm[3][W];     // populations 4, 7, 8   (c_y = -1)
+struct TileRings {
+  static constexpr int W = CW + 4;  // ring width: tile plus halo
+  real ux[3][W], uy[3][W], gy[3][W], gx[2][W];
+  real th[5][W], s[6][W];
+  real f0[2][3][W];  // populations 0, 1, 3   (c_y =  0)
+  real fp[3][3][W];  // populations 2, 5, 6   (c_y = +1)
+  real fm[3][W];     // populations 4, 7, 8   (c_y = -1)
+};
 
-  const DomainArgs &d = a.d;
+// One tile (bx, by) of one domain: src / dst point at plane 0 of the two
+// state buffers, planes are `d.plane` elements apart.  Ends with a barrier,
+// so the rings can be reused by the next tile.
+template <int CW>
+__device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0, real *dst0,
+                                           unsigned *status, const int rows, const int bx,
+                                           const int by, TileRings<CW> &R) {
   const int t = threadIdx.x;
-  int bid = blockIdx.x;
-  const int nblk = a.nbx * a.nby;
-  if (a.xcd_remap) {
-    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-    // contiguous range of tiles so halo re-reads stay in its L2.
-    const int per = (nblk + 7) >> 3;
-    const int xcd = bid & 7, k = bid >> 3;
-    const int full = nblk - (per - 1) * 8;  // XCDs that get `per` tiles
-    bid = xcd < full ? xcd * per + k : full * per + (xcd - full) * (per - 1) + k;
+  const real *src[kPlanes];
+  real *dst[kPlanes];
+#pragma unroll
+  for (int q = 0; q < kPlanes; ++q) {
+    src[q] = src0 + (long long)q * d.plane;
+    dst[q] = dst0 + (long long)q * d.plane;
   }
-  const int bx = bid % a.nbx, by = bid / a.nbx;
-  const int x0 = bx * CW, y0 = by * a.rows;
+  auto &r_ux = R.ux;
+  auto &r_uy = R.uy;
+  auto &r_gy = R.gy;
+  auto &r_gx = R.gx;
+  auto &r_th = R.th;
+  auto &r_s = R.s;
+  auto &r_f0 = R.f0;
+  auto &r_fp = R.fp;
+  auto &r_fm = R.fm;
+  const int x0 = bx * CW, y0 = by * rows;
   // lane -> ring position: tile lanes at 2..CW+1, halo lanes at 0, 1, CW+2, CW+3
   const int h = t - CW;
   const int ri = t < CW ? t + 2 : (h < 2 ? h : (h < 4 ? CW + h : 0));
@@ -234,7 +247,7 @@ __global__ __launch_bounds__(CW + 64) void k_step(StepArgs a) {
   const bool b_col = t < CW || h == 1 || h == 2;         // collision: ring 1..CW+2
   const int vx = x0 - 2 + ri;
   const int cx = map_index(vx, d.nx, d.bcx);
-  const int nrow = min(a.rows, d.ny - y0);
+  const int nrow = min(rows, d.ny - y0);
   const int nit = nrow + 4;
   const bool own_col = t < CW && vx < d.nx;
   const real cs2 = real(kCs2);
@@ -294,7 +307,7 @@ __global__ __launch_bounds__(CW + 64) void k_step(StepArgs a) {
     real ld[kPlanes];
     const unsigned off = row_off(0);
 #pragma unroll
-    for (int q = 0; q < kPlanes; ++q) ld[q] = load_at(a.src[q], off);
+    for (int q = 0; q < kPlanes; ++q) ld[q] = load_at(src[q], off);
     stage_a(0, ld);
   }
   __syncthreads();
@@ -306,7 +319,7 @@ __global__ __launch_bounds__(CW + 64) void k_step(StepArgs a) {
     if (do_a) {
       const unsigned off = row_off(i + 1);
 #pragma unroll
-      for (int q = 0; q < kPlanes; ++q) ld[q] = load_at(a.src[q], off);
+      for (int q = 0; q < kPlanes; ++q) ld[q] = load_at(src[q], off);
     }
     // A(i) has run for rows 0..i; s1_* holds row i, s0_* row i-1.
 
@@ -428,8 +441,8 @@ __global__ __launch_bounds__(CW + 64) void k_step(StepArgs a) {
       const real snew = sc - (advx + advy) + div_fast(d.lambda * lap + cB_phi, cB_rho * cB_th);
       const unsigned off = (unsigned)((y0 + k - 2) * d.nx + vx) * kEl;
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) store_stream(a.dst[q], off, Fo[q]);
-      store_stream(a.dst[9], off, snew);
+      for (int q = 0; q < kQ; ++q) store_stream(dst[q], off, Fo[q]);
+      store_stream(dst[9], off, snew);
     }
     cB_ux = nB_ux;
     cB_uy = nB_uy;
@@ -441,7 +454,53 @@ __global__ __launch_bounds__(CW + 64) void k_step(StepArgs a) {
     if (do_a) stage_a(i + 1, ld);
     __syncthreads();
   }
-  if (bad) atomicOr(a.status, 1u);
+  if (bad) atomicOr(status, 1u);
+}
+
+// Whole-domain step: one workgroup per tile.
+template <int CW>
+__global__ __launch_bounds__(CW + 64) void k_step(StepArgs a) {
+  __shared__ TileRings<CW> R;
+  int bid = blockIdx.x;
+  const int nblk = a.nbx * a.nby;
+  if (a.xcd_remap) {
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+    // contiguous range of tiles so halo re-reads stay in its L2.
+    const int per = (nblk + 7) >> 3;
+    const int xcd = bid & 7, k = bid >> 3;
+    const int full = nblk - (per - 1) * 8;  // XCDs that get `per` tiles
+    bid = xcd < full ? xcd * per + k : full * per + (xcd - full) * (per - 1) + k;
+  }
+  sweep_tile<CW>(a.d, a.src, a.dst, a.status, a.rows, bid % a.nbx, bid / a.nbx, R);
+}
+
+// Batched step: a persistent grid walks a list of (domain, tile) items,
+// statically round-robin (no atomics: the launch can be captured and
+// replayed).  Items of a domain whose divergence flag is set are skipped, so
+// a diverged domain freezes while the others go on.
+struct BatchArgs {
+  const DomainArgs *doms;
+  const long long *offs;  // element offset of each domain's state in a buffer
+  const int4 *items;      // (domain, bx, by, unused)
+  int nitems;
+  const real *src_buf;
+  real *dst_buf;
+  unsigned *status;       // one word per domain
+  int rows;
+};
+
+template <int CW>
+__global__ __launch_bounds__(CW + 64) void k_step_batch(BatchArgs a) {
+  __shared__ TileRings<CW> R;
+  for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+    const int4 w = a.items[it];
+    const int dm = __builtin_amdgcn_readfirstlane(w.x);
+    if (__builtin_amdgcn_readfirstlane(a.status[dm]) != 0u) continue;  // uniform skip
+    const DomainArgs d = a.doms[dm];
+    const long long off = a.offs[dm];
+    sweep_tile<CW>(d, a.src_buf + off, a.dst_buf + off, a.status + dm, a.rows,
+                   __builtin_amdgcn_readfirstlane(w.y), __builtin_amdgcn_readfirstlane(w.z), R);
+  }
 }
 
 // ------------------------------------------------------ initialisation

@@ -40,10 +40,8 @@ hipError_t step(const HostDomain &h, const void *src, void *dst, unsigned *statu
                 const TileShape &tile, hipStream_t st) {
   StepArgs a;
   a.d = to_device(h);
-  for (int q = 0; q < kPlanes; ++q) {
-    a.src[q] = (const real *)src + (long long)q * h.plane;
-    a.dst[q] = (real *)dst + (long long)q * h.plane;
-  }
+  a.src = (const real *)src;
+  a.dst = (real *)dst;
   a.status = status;
   a.rows = tile.rows;
   a.nbx = (h.nx + tile.bw - 1) / tile.bw;
@@ -126,6 +124,50 @@ hipError_t entropy(const void *rho, const void *theta, void *s, long long n, dou
   hipLaunchKernelGGL(k_entropy, dim3(grid_for(n, 256)), dim3(256), 0, st, (const real *)rho,
                      (const real *)theta, (real *)s, n, (real)(1.0 / cv), (real)(gamma - 1.0));
   return hipGetLastError();
+}
+
+size_t domain_args_bytes() { return sizeof(DomainArgs); }
+
+void pack_domains(const HostDomain *h, int count, void *host_out) {
+  DomainArgs *o = (DomainArgs *)host_out;
+  for (int k = 0; k < count; ++k) o[k] = to_device(h[k]);
+}
+
+hipError_t step_batch(const void *doms, const long long *offs, const void *items, int nitems,
+                      const void *src, void *dst, unsigned *status, int rows, int cw, int grid,
+                      hipStream_t st) {
+  BatchArgs a;
+  a.doms = (const DomainArgs *)doms;
+  a.offs = offs;
+  a.items = (const int4 *)items;
+  a.nitems = nitems;
+  a.src_buf = (const real *)src;
+  a.dst_buf = (real *)dst;
+  a.status = status;
+  a.rows = rows;
+  switch (cw) {
+  case 64:
+    hipLaunchKernelGGL(k_step_batch<64>, dim3(grid), dim3(64 + 64), 0, st, a);
+    break;
+  case 128:
+    hipLaunchKernelGGL(k_step_batch<128>, dim3(grid), dim3(128 + 64), 0, st, a);
+    break;
+  case 256:
+    hipLaunchKernelGGL(k_step_batch<256>, dim3(grid), dim3(256 + 64), 0, st, a);
+    break;
+  default:
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int batch_blocks_per_cu(int cw) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (cw == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch<64>, 128, 0);
+  if (cw == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch<128>, 192, 0);
+  if (cw == 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch<256>, 320, 0);
+  return e == hipSuccess && n > 0 ? n : 1;
 }
 
 }  // namespace HLBM_NS

@@ -36,6 +36,12 @@ struct TileShape {
                     double *out, hipStream_t st);                                           \
   hipError_t entropy(const void *rho, const void *theta, void *s, long long n, double gamma, \
                      hipStream_t st);                                                       \
+  size_t domain_args_bytes();                                                               \
+  void pack_domains(const HostDomain *h, int count, void *host_out);                        \
+  hipError_t step_batch(const void *doms, const long long *offs, const void *items,          \
+                        int nitems, const void *src, void *dst, unsigned *status, int rows, \
+                        int cw, int grid, hipStream_t st);                                  \
+  int batch_blocks_per_cu(int cw);                                                          \
   }
 
 HLBM_DECLARE_LAUNCHERS(f32)

@@ -1,0 +1,142 @@
+"""Batched engine: one persistent launch per step over many uneven domains.
+
+Per-node arithmetic is the single-domain kernel's, so a batched run must be
+bitwise identical to running each domain alone with the same tile shape."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import hlbm_inputs as hi
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2002_03644_amd import BatchSolver, Params, Solver  # noqa: E402
+
+SHAPES = [(64, 64), (100, 77), (130, 130), (257, 63), (33, 200), (5, 3), (300, 41)]
+
+
+def domain_set(dtype, poison=None):
+    params, fields = [], []
+    for k, (nx, ny) in enumerate(SHAPES):
+        mach = 0.2 + 0.15 * k
+        th = hi.theta_for_cfl(1.2 * mach)
+        if k % 2 == 0:
+            f = hi.vortex(nx, ny, nx / 2, ny / 2, max(2.0, min(nx, ny) / 8), mach, 0.1 * mach,
+                          theta_inf=th, angle=0.3 * k)
+        else:
+            f = hi.random_smooth(nx, ny, seed=k, amp=0.03, theta0=th, u0=(0.1, -0.05))
+        if poison == k:
+            f = (f[0], f[1] + 3.0, f[2], f[3])   # CFL far above 1: diverges
+        bc = "extrapolate" if k == 3 else "periodic"
+        params.append(Params(nx, ny, dtype=dtype, mu=1e-3 * (1 + k), sigma=0.1 * k,
+                             bc_x=bc, theta_ref=th, tile_w=128, tile_h=32))
+        fields.append(f)
+    return params, fields
+
+
+def singles(params, fields, steps):
+    out = []
+    for p, f in zip(params, fields):
+        S = Solver(p, *f[:3], theta=f[3])
+        S.step(steps)
+        out.append({k: v.clone() for k, v in S.moments().items()})
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_bitwise_equals_single_domains(dtype, graph):
+    params, fields = domain_set(dtype)
+    B = BatchSolver(params, fields)
+    B.set_tile(128, 32)
+    B.step(23, graph=graph)
+    mb = B.moments()
+    ms = singles(params, fields, 23)
+    for k in range(len(params)):
+        for key in ("rho", "ux", "uy", "s"):
+            assert torch.equal(mb[k][key], ms[k][key]), (k, key)
+    assert B.status()[0] == 0
+
+
+def test_graph_replays_match_eager_between_eager_work():
+    """Replays of the captured graph, interleaved with unrelated eager work and
+    synchronisations, equal an eager run after every replay."""
+    params, fields = domain_set("f32")
+    A = BatchSolver(params, fields)
+    E = BatchSolver(params, fields)
+    x = torch.randn(512, 512, device="cuda")
+    for rep in range(5):
+        A.step(6, graph=True)
+        E.step(6, graph=False)
+        y = (x @ x).sum()          # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(y)
+        ma, me = A.moments(), E.moments()
+        for k in range(len(params)):
+            assert torch.equal(ma[k]["rho"], me[k]["rho"]), (rep, k)
+            assert torch.equal(ma[k]["s"], me[k]["s"]), (rep, k)
+    assert A.steps == E.steps == 30
+
+
+def test_diverged_domain_is_isolated():
+    params, fields = domain_set("f32", poison=2)
+    B = BatchSolver(params, fields)
+    B.set_tile(128, 32)
+    B.step(40)
+    bad, flags = B.status()
+    assert bad == 1 and flags[2] == 1 and flags.sum() == 1
+    mb = B.moments()
+    keep = [k for k in range(len(params)) if k != 2]
+    ms = singles([params[k] for k in keep], [fields[k] for k in keep], 40)
+    for j, k in enumerate(keep):
+        assert torch.equal(mb[k]["rho"], ms[j]["rho"]), k
+
+
+def test_autotune_restores_state_and_caches(tmp_path):
+    params, fields = domain_set("f32")
+    B = BatchSolver(params, fields)
+    B.step(4)
+    before = [m["rho"].clone() for m in B.moments()]
+    cache = str(tmp_path / "tune.json")
+    w, h = B.autotune(steps=2, cache_path=cache)
+    assert w in (64, 128, 256) and h in (16, 32, 64, 128)
+    after = [m["rho"] for m in B.moments()]
+    for a, b in zip(before, after):
+        assert torch.equal(a, b)
+    with open(cache) as fh:
+        assert json.load(fh)[B.signature()] == [w, h]
+    assert B.autotune(cache_path=cache) == (w, h)   # served from the cache
+
+
+def test_batch_256_domains_seed0():
+    """The 256-domain batch (log-uniform sizes 64..1016, vortex or turbulence,
+    Mach 0.1-2.0, seed 0): 20 graph-replayed steps; domains that stay finite
+    are bitwise equal to their single-domain runs (checked on a sample), and
+    the divergence flags agree with a finite-value scan."""
+    specs = hi.batch_specs(256, seed=0)
+    params, fields = [], []
+    for sp in specs:
+        f = hi.batch_domain_fields(sp)
+        params.append(Params(sp.n, sp.n, dtype="f32", mu=1e-3, sigma=0.0, theta_ref=sp.theta,
+                             tile_w=128, tile_h=32))
+        fields.append(f)
+    assert sum(p.nx * p.ny for p in params) == 58630144
+    B = BatchSolver(params, fields)
+    B.set_tile(128, 32)
+    B.step(20, graph=True)
+    bad, flags = B.status()
+    mb = B.moments()
+    for k in range(256):
+        finite = bool(torch.isfinite(mb[k]["rho"]).all())
+        if flags[k] == 0:
+            assert finite, k
+    print(f"256-domain batch: {bad} domains diverged within 20 steps")
+    for k in (0, 5, 17, 100, 255):
+        if flags[k]:
+            continue
+        S = Solver(params[k], *fields[k][:3], theta=fields[k][3])
+        S.step(20)
+        assert torch.equal(S.moments()["rho"], mb[k]["rho"]), k

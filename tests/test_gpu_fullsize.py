@@ -1,0 +1,113 @@
+"""Parity at full size, in the launch configuration bench.py times.
+
+One step of a node depends only on the state within radius 2, so the oracle
+can check a full-size GPU step on small patches: take the GPU state around a
+sampled node, step the patch once on the CPU, and compare the patch interior
+(nodes at least 2 from the patch edge) with the GPU's next state."""
+import numpy as np
+import pytest
+
+import hlbm_inputs as hi
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2002_03644_amd import HLBM_OK, Params, Solver  # noqa: E402
+
+P = 12      # patch edge
+INNER = 2   # rim whose nodes see outside the patch
+
+
+def take_patch(arr, y0, x0, ny, nx, wrap_y, wrap_x):
+    """arr: torch [..., ny, nx] on the GPU -> numpy FP64 patch [..., P, P]."""
+    ys = torch.arange(y0, y0 + P, device=arr.device)
+    xs = torch.arange(x0, x0 + P, device=arr.device)
+    ys = ys % ny if wrap_y else ys.clamp(0, ny - 1)
+    xs = xs % nx if wrap_x else xs.clamp(0, nx - 1)
+    sub = arr.index_select(-2, ys).index_select(-1, xs)
+    return sub.double().cpu().numpy()
+
+
+def patch_check(S, params, samples, steps_before, tol_F, tol_s, bc_x="periodic"):
+    nx, ny = params.nx, params.ny
+    S.step(steps_before)
+    F0 = S.populations()
+    s0 = S.moments()["s"]
+    S.step(1)
+    F1 = S.populations()
+    s1 = S.moments()["s"]
+    assert S.status()[0] == HLBM_OK
+    worst = (0.0, 0.0)
+    for (y, x) in samples:
+        # patch origin; at an extrapolated x boundary the patch starts at the
+        # boundary so the oracle's own boundary rule applies there
+        x0 = x - P // 2
+        bx = "periodic"
+        if bc_x == "extrapolate" and (x0 < 0 or x0 + P > nx):
+            x0 = 0 if x0 < 0 else nx - P
+            bx = "extrapolate"
+        y0 = y - P // 2
+        pf0 = take_patch(F0, y0, x0, ny, nx, True, bc_x == "periodic")
+        ps0 = take_patch(s0, y0, x0, ny, nx, True, bc_x == "periodic")
+        pf1 = take_patch(F1, y0, x0, ny, nx, True, bc_x == "periodic")
+        ps1 = take_patch(s1, y0, x0, ny, nx, True, bc_x == "periodic")
+        op = oracle.OracleParams(P, P, gamma=params.gamma, mu=params.mu, sigma=params.sigma,
+                                 prandtl=params.prandtl, phi_mode=params.phi_mode,
+                                 bc_x="extrapolate", bc_y="extrapolate", sgn_eps=params.sgn_eps)
+        rho = pf0.sum(0)
+        O = oracle.OracleSolver(op, rho, np.zeros_like(rho), np.zeros_like(rho), s=ps0)
+        O.set_state(pf0, ps0)
+        O.step(1)
+        Fo, so = O.state()
+        # interior: at least INNER from every patch edge that is not a true
+        # extrapolated boundary of the domain
+        xl = 0 if (bx == "extrapolate" and x0 == 0) else INNER
+        xr = P if (bx == "extrapolate" and x0 + P == nx) else P - INNER
+        sl = (slice(None), slice(INNER, P - INNER), slice(xl, xr))
+        dF = np.abs(Fo[sl] - pf1[sl]).max()
+        ds = np.abs(so[sl[1:]] - ps1[sl[1:]]).max()
+        worst = (max(worst[0], dF), max(worst[1], ds))
+        assert dF < tol_F, ((y, x), dF)
+        assert ds < tol_s, ((y, x), ds)
+    print("worst |dF|, |ds|:", worst)
+
+
+def test_f32_turbulence_8192_sampled_one_step():
+    """Decaying turbulence 8192^2, FP32, default tiles (as bench.py): after 20
+    steps, one more GPU step matches the oracle's step of the same FP32 state
+    on 80 patches -- random nodes plus tile seams (x = 127, 128), strip seams
+    (y = 31, 32) and the periodic corners.  FP32 arithmetic: 1e-6 on F
+    (values ~0.01-0.4), 2e-6 on s (|s| ~ 1.3)."""
+    n = 8192
+    r, u, v, t = hi.turbulence(n, 0.5, hi.THETA_PAPER, seed=0)
+    params = Params(n, n, dtype="f32", mu=1e-3, sigma=0.0)
+    dev = torch.device("cuda:0")
+    f = [torch.from_numpy(a.astype(np.float32)).to(dev) for a in (r, u, v, t)]
+    del r, u, v, t
+    S = Solver(params, *f[:3], theta=f[3], device=dev)
+    del f
+    rng = np.random.default_rng(7)
+    samples = [(int(a), int(b)) for a, b in rng.integers(0, n, size=(64, 2))]
+    samples += [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (31, 127), (32, 128),
+                (31, 128), (32, 127), (4095, 4096), (4096, 4095), (n - 33, 255), (5, 8191),
+                (8191, 3), (100, 128 * 40), (32 * 200, 77), (32 * 255 + 31, 128 * 63 + 127)]
+    patch_check(S, params, samples, 20, tol_F=1e-6, tol_s=2e-6)
+
+
+def test_f64_mach2_2048x512_sampled_one_step():
+    """Mach-2 normal shock 2048 x 512, FP64, x extrapolated: one step matches
+    the oracle at 1e-13 absolute on patches across the shock, at both x
+    boundaries and at tile and strip seams."""
+    nx, ny = 2048, 512
+    fields = hi.normal_shock(nx, ny, mach=2.0, theta1=0.1, perturb=1e-3, seed=0)
+    s = oracle.entropy_from_theta(fields[0], fields[3], 1.4)
+    params = Params(nx, ny, dtype="f64", mu=1e-3, sigma=0.0, phi_mode="fd",
+                    bc_x="extrapolate")
+    S = Solver(params, *fields[:3], s=s)
+    rng = np.random.default_rng(3)
+    samples = [(int(a), int(b)) for a, b in zip(rng.integers(0, ny, 24),
+                                                rng.integers(0, nx, 24))]
+    samples += [(10, 0), (20, 1), (30, nx - 1), (40, nx - 2), (0, 1024), (511, 1023),
+                (31, 127), (32, 128), (200, 1020), (201, 1030)]
+    patch_check(S, params, samples, 50, tol_F=1e-13, tol_s=1e-13, bc_x="extrapolate")
