@@ -12,7 +12,13 @@ it.  It defines what the GPU's BF16-MFMA kernels compute:
   in[y + dy - 1, x + dx - 1, ci] w[dy, dx, ci, co] + b[co]);
 * mean-squared-error loss and its exact gradient (reverse mode written out
   layer by layer);
-* the Adam update (Kingma & Ba) with bias correction.
+* the Adam update (Kingma & Ba) with bias correction;
+* a storage-precision variant of the forward and backward passes
+  (``loss_and_grads_stored``) in which every tensor the GPU path keeps in
+  BF16 -- the standardised input, the weights, the hidden activations and the
+  back-propagated gradients -- is rounded to BF16 (round to nearest, ties to
+  even) where it is stored, all arithmetic staying FP64.  Parity of the BF16
+  kernels is checked against it.
 
 Arrays are NHWC: [batch, y, x, channel]; weights [3, 3, c_in, c_out].
 """
@@ -47,6 +53,14 @@ def conv3x3_grad(x, w, gout):
             gx += np.roll(np.roll(back, dy - 1, axis=1), dx - 1, axis=2)
     gb = gout.sum(axis=(0, 1, 2))
     return gx, gw, gb
+
+
+def bf16(a):
+    """Round to the nearest BF16 value (ties to even), returned as float64:
+    the float32 bit pattern with its low 16 bits rounded away."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
 def init_params(seed=0):
@@ -130,3 +144,66 @@ def restrict(rho, ux, uy, theta, factor):
 
     rc = bmean(rho)
     return rc, bmean(rho * ux) / rc, bmean(rho * uy) / rc, bmean(rho * theta) / rc
+
+
+def forward_stored(params, x):
+    """Forward pass with BF16 storage of input, weights and hidden
+    activations (biases and the output stay unrounded)."""
+    h = bf16(x)
+    acts = [h]
+    for k, (w, b) in enumerate(params):
+        z = conv3x3(h, bf16(w), b)
+        if k < 2:
+            h = bf16(np.maximum(z, 0.0))
+            acts.append(h)
+        else:
+            h = z
+    return h, acts
+
+
+def loss_and_grads_stored(params, x, target):
+    """MSE loss and parameter gradients with BF16 storage of the output
+    gradient and of the gradients passed back through each hidden layer; the
+    ReLU mask is taken from the stored activation (a > 0)."""
+    y, acts = forward_stored(params, x)
+    n = y.size
+    diff = y - target
+    loss = float((diff * diff).sum() / n)
+    g = bf16(2.0 * diff / n)
+    grads = [None] * 3
+    for k in (2, 1, 0):
+        gx, gw, gb = conv3x3_grad(acts[k], bf16(params[k][0]), g)
+        grads[k] = (gw, gb)
+        if k > 0:
+            g = bf16(gx * (acts[k] > 0))
+    return loss, grads
+
+
+def flatten(params):
+    """Canonical parameter vector: per layer the weights [3][3][c_in][c_out]
+    then the biases."""
+    return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params])
+
+
+def unflatten(vec):
+    out, o = [], 0
+    for k in range(3):
+        ci, co = CHANNELS[k], CHANNELS[k + 1]
+        nw = 9 * ci * co
+        out.append((np.asarray(vec[o:o + nw], dtype=np.float64).reshape(3, 3, ci, co),
+                    np.asarray(vec[o + nw:o + nw + co], dtype=np.float64)))
+        o += nw + co
+    return out
+
+
+def apply_correction(rho, ux, uy, theta, d, conserve=True):
+    """Corrected moments of one domain: rho' = rho + d_rho - a,
+    rho' u' = rho' (u + d_u) - b, theta' = theta + d_theta, where a = <d_rho>
+    and b = <(rho + d_rho)(u + d_u) - rho u> - a <u + d_u> keep the total mass
+    and momentum (a = b = 0 without conservation)."""
+    dr, du, dv, dt = d
+    a = dr.mean() if conserve else 0.0
+    bx = ((rho + dr) * (ux + du) - rho * ux).mean() - a * (ux + du).mean() if conserve else 0.0
+    by = ((rho + dr) * (uy + dv) - rho * uy).mean() - a * (uy + dv).mean() if conserve else 0.0
+    r2 = rho + dr - a
+    return r2, (ux + du) - bx / r2, (uy + dv) - by / r2, theta + dt

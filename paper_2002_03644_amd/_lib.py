@@ -86,6 +86,24 @@ def lib():
             "hlbm_batch_nodes": (i64, [vp]),
             "hlbm_batch_steps_done": (i64, [vp]),
             "hlbm_batch_destroy": (None, [vp]),
+            # learned closure (include/hlbm_nn.h)
+            "hlbm_cnn_workspace_bytes": (sz, [i32, i32, i32]),
+            "hlbm_cnn_init": (ctypes.c_int, [ctypes.POINTER(vp), i32, i32, i32, vp, sz, vp, vp]),
+            "hlbm_cnn_set_params": (ctypes.c_int, [vp, vp, vp]),
+            "hlbm_cnn_get_params": (ctypes.c_int, [vp, vp, vp]),
+            "hlbm_cnn_get_grads": (ctypes.c_int, [vp, vp, vp]),
+            "hlbm_cnn_set_norm": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_float)]),
+            "hlbm_cnn_forward": (ctypes.c_int, [vp, vp, i64, i64, vp, i32, vp, i64, i64, vp]),
+            "hlbm_cnn_loss_grad": (ctypes.c_int, [vp, vp, i64, i64, vp, i64, i64, vp, i32, vp,
+                                                  vp]),
+            "hlbm_cnn_adam": (ctypes.c_int, [vp, ctypes.c_float, vp]),
+            "hlbm_cnn_train_step": (ctypes.c_int, [vp, vp, i64, i64, vp, i64, i64, vp, i32,
+                                                   ctypes.c_float, vp, vp]),
+            "hlbm_cnn_destroy": (None, [vp]),
+            "hlbm_restrict": (ctypes.c_int, [vp, vp, vp, vp, i32, i32, i32, i32, vp, i64, i64,
+                                             vp]),
+            "hlbm_batch_correct": (ctypes.c_int, [vp, vp, vp, i32, vp]),
+            "hlbm_closure_step": (ctypes.c_int, [vp, vp, i32, i32, i32, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -383,6 +401,23 @@ class BatchSolver:
         _check(lib().hlbm_batch_load_state(self.h, _ptr(buf), _stream(self.stream)),
                "hlbm_batch_load_state")
         self._leave()
+
+    def correct(self, x, delta, conserve=True):
+        """Apply increments ``delta`` to moments ``x`` (both [4][count][ny nx]
+        float32 device tensors) of an FP32 batch of equal-size domains."""
+        self._enter()
+        _check(lib().hlbm_batch_correct(self.h, _ptr(x), _ptr(delta), int(bool(conserve)),
+                                        _stream(self.stream)), "hlbm_batch_correct")
+        self._leave()
+
+    def closure_step(self, net, n=1, conserve=True, graph=True):
+        """n steps, each followed by the network's correction."""
+        self._enter()
+        _check(lib().hlbm_closure_step(self.h, net.h, int(n), int(bool(conserve)),
+                                       int(bool(graph)), _stream(self.stream)),
+               "hlbm_closure_step")
+        self._leave()
+        return self
 
     def signature(self):
         import hashlib

@@ -1,0 +1,133 @@
+"""Binding of the learned closure (include/hlbm_nn.h): argument marshalling
+only -- the network's forward and backward passes, Adam and the restriction
+run in the library's HIP kernels."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._lib import HLBM_EINVAL, HlbmError, _check, _ptr, _stream, lib
+
+N_PARAMS = 11588
+
+
+def _f32(t, device):
+    import torch
+    return torch.as_tensor(t).to(device=device, dtype=torch.float32).contiguous()
+
+
+class CNN:
+    """The 4 -> 32 -> 32 -> 4 closure network for batches of up to
+    ``max_batch`` fields of ny x nx.  Field batches are float32 device tensors
+    addressed as x[s * sstride + c * cstride + i]; a [S][4][ny][nx] tensor
+    has sstride 4 ny nx and cstride ny nx (the defaults)."""
+
+    def __init__(self, max_batch, ny, nx, params, device="cuda"):
+        import torch
+        self.device = torch.device(device)
+        self.max_batch, self.ny, self.nx = int(max_batch), int(ny), int(nx)
+        nbytes = lib().hlbm_cnn_workspace_bytes(self.max_batch, self.ny, self.nx)
+        if nbytes == 0:
+            raise HlbmError(HLBM_EINVAL, "hlbm_cnn_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        p = _f32(params, self.device).reshape(-1)
+        if p.numel() != N_PARAMS:
+            raise ValueError(f"expected {N_PARAMS} parameters")
+        h = ctypes.c_void_p()
+        _check(lib().hlbm_cnn_init(ctypes.byref(h), self.max_batch, self.ny, self.nx,
+                                   _ptr(self.workspace), nbytes, _ptr(p), _stream()),
+               "hlbm_cnn_init")
+        self.h = h
+        self.norm = np.array([0, 0, 0, 0, 1, 1, 1, 1, 0, 0, 0, 0, 1, 1, 1, 1], np.float32)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().hlbm_cnn_destroy(h)
+            self.h = None
+
+    def set_params(self, params):
+        p = _f32(params, self.device).reshape(-1)
+        _check(lib().hlbm_cnn_set_params(self.h, _ptr(p), _stream()), "hlbm_cnn_set_params")
+
+    def params(self):
+        import torch
+        out = torch.empty(N_PARAMS, dtype=torch.float32, device=self.device)
+        _check(lib().hlbm_cnn_get_params(self.h, _ptr(out), _stream()), "hlbm_cnn_get_params")
+        return out
+
+    def grads(self):
+        import torch
+        out = torch.empty(N_PARAMS, dtype=torch.float32, device=self.device)
+        _check(lib().hlbm_cnn_get_grads(self.h, _ptr(out), _stream()), "hlbm_cnn_get_grads")
+        return out
+
+    def set_norm(self, in_mean, in_std, out_mean, out_std):
+        norm = np.concatenate([in_mean, in_std, out_mean, out_std]).astype(np.float32)
+        arr = (ctypes.c_float * 16)(*norm.tolist())
+        _check(lib().hlbm_cnn_set_norm(self.h, arr), "hlbm_cnn_set_norm")
+        self.norm = norm
+
+    def _strides(self, sstride, cstride):
+        n = self.ny * self.nx
+        return (4 * n if sstride is None else int(sstride)), (n if cstride is None else int(cstride))
+
+    def forward(self, x, batch=None, idx=None, sstride=None, cstride=None, out=None):
+        """Raw increments [batch][4][ny][nx] for the fields x."""
+        import torch
+        sb, sc = self._strides(sstride, cstride)
+        batch = int(batch if batch is not None else (len(idx) if idx is not None else
+                                                     x.numel() // (4 * self.ny * self.nx)))
+        if out is None:
+            out = torch.empty(batch, 4, self.ny, self.nx, dtype=torch.float32, device=self.device)
+        n = self.ny * self.nx
+        _check(lib().hlbm_cnn_forward(self.h, _ptr(x), sb, sc, _ptr(idx), batch, _ptr(out),
+                                      4 * n, n, _stream()), "hlbm_cnn_forward")
+        return out
+
+    def loss_grad(self, x, target, batch=None, idx=None, sstride=None, cstride=None,
+                  t_sstride=None, t_cstride=None, loss=None):
+        import torch
+        sb, sc = self._strides(sstride, cstride)
+        tsb, tsc = self._strides(t_sstride, t_cstride)
+        batch = int(batch if batch is not None else (len(idx) if idx is not None else
+                                                     x.numel() // (4 * self.ny * self.nx)))
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(lib().hlbm_cnn_loss_grad(self.h, _ptr(x), sb, sc, _ptr(target), tsb, tsc,
+                                        _ptr(idx), batch, _ptr(loss), _stream()),
+               "hlbm_cnn_loss_grad")
+        return loss
+
+    def adam(self, lr):
+        return _check(lib().hlbm_cnn_adam(self.h, float(lr), _stream()), "hlbm_cnn_adam")
+
+    def train_step(self, x, target, lr, batch=None, idx=None, sstride=None, cstride=None,
+                   t_sstride=None, t_cstride=None, loss=None):
+        import torch
+        sb, sc = self._strides(sstride, cstride)
+        tsb, tsc = self._strides(t_sstride, t_cstride)
+        batch = int(batch if batch is not None else (len(idx) if idx is not None else
+                                                     x.numel() // (4 * self.ny * self.nx)))
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(lib().hlbm_cnn_train_step(self.h, _ptr(x), sb, sc, _ptr(target), tsb, tsc,
+                                         _ptr(idx), batch, float(lr), _ptr(loss), _stream()),
+               "hlbm_cnn_train_step")
+        return loss
+
+
+def restrict(rho, ux, uy, theta, factor, batch=1, out=None):
+    """Conservative block-mean restriction of [batch][ny][nx] float32 fields
+    to [batch][4][ny/f][nx/f] (rho, u_x, u_y, theta)."""
+    import torch
+    ny, nx = rho.shape[-2], rho.shape[-1]
+    nyc, nxc = ny // factor, nx // factor
+    if out is None:
+        out = torch.empty(batch, 4, nyc, nxc, dtype=torch.float32, device=rho.device)
+    n = nyc * nxc
+    _check(lib().hlbm_restrict(_ptr(rho), _ptr(ux), _ptr(uy), _ptr(theta), int(batch), int(ny),
+                               int(nx), int(factor), _ptr(out), 4 * n, n, _stream()),
+           "hlbm_restrict")
+    return out

@@ -23,6 +23,7 @@ UNITS = {
     "hlbm_api.hip": [],
     "hlbm_kernels_f32.hip": ["-ffp-contract=on"],
     "hlbm_kernels_f64.hip": ["-ffp-contract=off"],
+    "hlbm_nn.hip": ["-ffp-contract=on"],
 }
 
 

@@ -13,6 +13,8 @@
 
 #include "hlbm.h"
 #include "hlbm_launch.hpp"
+#include "hlbm_nn.h"
+#include "hlbm_nn_internal.hpp"
 
 namespace {
 
@@ -348,12 +350,16 @@ struct hlbm_batch {
   std::vector<long long> field_offs;  // offset of each domain in the concatenated fields
   std::vector<long long> state_elems; // ten planes of each domain
   char *ws = nullptr;
-  size_t off_buf1 = 0, off_doms = 0, off_offs = 0, off_items = 0, off_stat = 0, total = 0;
+  size_t off_buf1 = 0, off_doms = 0, off_offs = 0, off_items = 0, off_stat = 0, off_corr = 0;
+  size_t total = 0;
   size_t state_bytes = 0;             // one buffer
   int max_items = 0, nitems = 0, tile_w = 128, tile_h = 32, grid = 1, cur = 0, ncu = 1;
   int64_t steps = 0, nodes = 0;
   hipGraphExec_t graph = nullptr;
   int graph_cur = -1;
+  hipGraphExec_t cgraph = nullptr;    // captured corrected steps (hlbm_closure_step)
+  int cgraph_cur = -1, cgraph_conserve = -1;
+  const hlbm_cnn *cgraph_net = nullptr;
 };
 
 namespace {
@@ -410,7 +416,10 @@ void batch_layout(hlbm_batch *b) {
   b->off_offs = b->off_doms + round_up(dbytes * b->count, kAlign);
   b->off_items = b->off_offs + round_up(sizeof(long long) * b->count, kAlign);
   b->off_stat = b->off_items + round_up(sizeof(int) * 4 * (size_t)b->max_items, kAlign);
-  b->total = b->off_stat + round_up(sizeof(unsigned) * b->count, kAlign);
+  b->off_corr = b->off_stat + round_up(sizeof(unsigned) * b->count, kAlign);
+  b->total = b->off_corr + round_up(std::max(hlbm::f32::correct_partials_bytes(b->count),
+                                             hlbm::f64::correct_partials_bytes(b->count)),
+                                    kAlign);
 }
 
 int batch_validate(const hlbm_params *p, int32_t count) {
@@ -439,6 +448,10 @@ hipError_t batch_upload_items(hlbm_batch *b, int tw, int th, hipStream_t st) {
   if (b->graph) {
     hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
+  }
+  if (b->cgraph) {
+    hipGraphExecDestroy(b->cgraph);
+    b->cgraph = nullptr;
   }
   return hipSuccess;
 }
@@ -687,7 +700,108 @@ int64_t hlbm_batch_steps_done(const hlbm_batch *b) { return b ? b->steps : -1; }
 void hlbm_batch_destroy(hlbm_batch *b) {
   if (!b) return;
   if (b->graph) hipGraphExecDestroy(b->graph);
+  if (b->cgraph) hipGraphExecDestroy(b->cgraph);
   delete b;
+}
+
+}  // extern "C"
+
+// ======================================================================
+// Learned-closure coupling
+// ======================================================================
+namespace {
+
+// every domain of one size, FP32
+bool closure_ok(const hlbm_batch *b) {
+  if (!b || b->dtype != HLBM_F32) return false;
+  for (int k = 1; k < b->count; ++k)
+    if (b->params[k].nx != b->params[0].nx || b->params[k].ny != b->params[0].ny) return false;
+  return true;
+}
+
+hipError_t correct_launch(hlbm_batch *b, const float *x, const float *delta, int conserve,
+                          hipStream_t st) {
+  char *state = b->ws + (b->cur ? b->off_buf1 : 0);
+  const long long n = (long long)b->params[0].nx * b->params[0].ny;
+  return hlbm::f32::correct(b->ws + b->off_doms, (const long long *)(b->ws + b->off_offs),
+                            b->count, n, state, x, delta, (double *)(b->ws + b->off_corr),
+                            conserve, st);
+}
+
+// one corrected step from buffer b->cur; advances b->cur
+int closure_once(hlbm_batch *b, hlbm_cnn *c, int conserve, hipStream_t st) {
+  if (batch_launch(b, b->cur, st) != hipSuccess) return HLBM_EHIP;
+  b->cur ^= 1;
+  float *x = hlbm_cnn_io(c, 0), *d = hlbm_cnn_io(c, 1);
+  const long long n = (long long)b->params[0].nx * b->params[0].ny;
+  const long long N = n * b->count;
+  int rc = hlbm_batch_moments(b, x, x + N, x + 2 * N, nullptr, x + 3 * N, st);
+  if (rc != HLBM_OK) return rc;
+  rc = hlbm_cnn_forward(c, x, n, N, nullptr, b->count, d, n, N, st);
+  if (rc != HLBM_OK) return rc;
+  return correct_launch(b, x, d, conserve, st) == hipSuccess ? HLBM_OK : HLBM_EHIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hlbm_batch_correct(hlbm_batch *b, const float *x, const float *delta, int32_t conserve,
+                       hlbm_stream_t stream) {
+  if (!closure_ok(b) || !x || !delta) return HLBM_EINVAL;
+  return hip_status(correct_launch(b, x, delta, conserve ? 1 : 0, (hipStream_t)stream));
+}
+
+int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t nsteps, int32_t conserve,
+                      int32_t use_graph, hlbm_stream_t stream) {
+  if (!closure_ok(b) || !c || nsteps < 0) return HLBM_EINVAL;
+  if (hlbm_cnn_max_batch(c) < b->count || hlbm_cnn_ny(c) != b->params[0].ny ||
+      hlbm_cnn_nx(c) != b->params[0].nx)
+    return HLBM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (use_graph && !st) return HLBM_EINVAL;
+  conserve = conserve ? 1 : 0;
+  int n = nsteps;
+  if (use_graph && n >= 2) {
+    if (!b->cgraph || b->cgraph_cur != b->cur || b->cgraph_net != c ||
+        b->cgraph_conserve != conserve) {
+      if (b->cgraph) {
+        hipGraphExecDestroy(b->cgraph);
+        b->cgraph = nullptr;
+      }
+      const int cur0 = b->cur;
+      hipGraph_t g = nullptr;
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return HLBM_EHIP;
+      int rc1 = closure_once(b, c, conserve, st);
+      int rc2 = rc1 == HLBM_OK ? closure_once(b, c, conserve, st) : rc1;
+      hipError_t e = hipStreamEndCapture(st, &g);
+      b->cur = cur0;   // capture only recorded the launches
+      if (rc1 != HLBM_OK || rc2 != HLBM_OK || e != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return HLBM_EHIP;
+      }
+      e = hipGraphInstantiate(&b->cgraph, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        b->cgraph = nullptr;
+        return HLBM_EHIP;
+      }
+      b->cgraph_cur = b->cur;
+      b->cgraph_net = c;
+      b->cgraph_conserve = conserve;
+    }
+    for (; n >= 2; n -= 2) {
+      if (hipGraphLaunch(b->cgraph, st) != hipSuccess) return HLBM_EHIP;
+      b->steps += 2;
+    }
+  }
+  for (; n > 0; --n) {
+    const int rc = closure_once(b, c, conserve, st);
+    if (rc != HLBM_OK) return rc;
+    b->steps++;
+  }
+  return HLBM_OK;
 }
 
 }  // extern "C"

@@ -1,6 +1,7 @@
 // Launchers of one precision; included by hlbm_kernels_f32.hip and
 // hlbm_kernels_f64.hip after HLBM_REAL and HLBM_NS are defined.
 #include "hlbm_device.hpp"
+#include "closure_device.hpp"
 #include "hlbm_launch.hpp"
 
 namespace hlbm {
@@ -159,6 +160,31 @@ hipError_t step_batch(const void *doms, const long long *offs, const void *items
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t correct(const void *doms, const long long *offs, int count, long long n, void *state,
+                   const float *x, const float *dl, double *partials, int conserve,
+                   hipStream_t st) {
+  CorrArgs a;
+  a.doms = (const DomainArgs *)doms;
+  a.offs = offs;
+  a.state = (real *)state;
+  a.x = x;
+  a.dl = dl;
+  a.n = n;
+  a.sc = n * count;
+  a.partials = partials;
+  a.conserve = conserve;
+  if (conserve)
+    hipLaunchKernelGGL(k_corr_sums, dim3(kCorrParts, count), dim3(kCorrThreads), 0, st, a);
+  const long long per = (n + kCorrThreads - 1) / kCorrThreads;
+  const int gx = (int)(per < 256 ? per : 256);
+  hipLaunchKernelGGL(k_corr_apply, dim3(gx, count), dim3(kCorrThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+size_t correct_partials_bytes(int count) {
+  return sizeof(double) * kCorrParts * kCorrVals * (size_t)count;
 }
 
 int batch_blocks_per_cu(int cw) {

@@ -42,6 +42,10 @@ struct TileShape {
                         int nitems, const void *src, void *dst, unsigned *status, int rows, \
                         int cw, int grid, hipStream_t st);                                  \
   int batch_blocks_per_cu(int cw);                                                          \
+  hipError_t correct(const void *doms, const long long *offs, int count, long long n,       \
+                     void *state, const float *x, const float *dl, double *partials,        \
+                     int conserve, hipStream_t st);                                         \
+  size_t correct_partials_bytes(int count);                                                 \
   }
 
 HLBM_DECLARE_LAUNCHERS(f32)

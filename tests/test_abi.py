@@ -1,6 +1,7 @@
 """C-ABI contract checks that need no GPU: the library loads, exports every
-symbol include/hlbm.h declares, and its host-only functions validate
-parameters and size workspaces."""
+symbol the headers under include/ declare, and its host-only functions
+validate parameters and size workspaces."""
+import glob
 import ctypes
 import os
 import re
@@ -8,14 +9,15 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "hlbm.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"\b(hlbm_[a-z0-9_]+)\s*\(", text)
-    return sorted(set(names))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"\b(hlbm_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_core_entry_points():
@@ -88,3 +90,23 @@ def test_strerror_covers_codes():
     from paper_2002_03644_amd import strerror
     for c in (0, 1, -1, -2, -3, -4, -5):
         assert strerror(c) and "unknown" not in strerror(c)
+
+
+def test_nn_header_declares_the_closure_entry_points():
+    names = declared_functions()
+    for n in ("hlbm_cnn_init", "hlbm_cnn_forward", "hlbm_cnn_loss_grad", "hlbm_cnn_adam",
+              "hlbm_restrict", "hlbm_batch_correct", "hlbm_closure_step"):
+        assert n in names
+
+
+@pytest.mark.parametrize("dims,ok", [((8, 256, 256), True), ((1, 4, 32), True),
+                                     ((0, 256, 256), False), ((8, 250, 256), False),
+                                     ((8, 256, 48), False), ((8, 2, 32), False),
+                                     ((40000, 256, 256), False)])
+def test_cnn_workspace_validates_dims(dims, ok):
+    from paper_2002_03644_amd import _lib
+    n = _lib.lib().hlbm_cnn_workspace_bytes(*dims)
+    assert (n > 0) == ok
+    if ok:   # at least the activations: 4 + 32 + 32 (+ gradients) BF16 channels per pixel
+        b, h, w = dims
+        assert n >= b * h * w * 2 * (4 + 32 + 32 + 4 + 32 + 32)

@@ -85,3 +85,75 @@ def test_restriction_conserves_block_totals():
 def test_parameter_count():
     params = C.init_params()
     assert sum(w.size + b.size for w, b in params) == 11588
+
+
+def test_bf16_rounding_ties_to_even_and_matches_torch():
+    one = np.float64(1.0)
+    assert C.bf16(np.array([one + 2.0 ** -8]))[0] == 1.0            # tie -> even (1)
+    assert C.bf16(np.array([one + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6   # tie -> even
+    assert C.bf16(np.array([one + 2.0 ** -8 + 2.0 ** -20]))[0] == 1.0 + 2.0 ** -7
+    torch = pytest.importorskip("torch")
+    x = np.random.default_rng(5).normal(size=10000) * 10.0 ** np.random.default_rng(6).integers(-20, 20, 10000)
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(C.bf16(x), ref)
+
+
+def test_stored_precision_variant_is_close_and_exact_on_representable_data():
+    """With inputs and weights already BF16-representable and activations
+    that stay representable (small-integer data), the stored-precision
+    passes equal the FP64 ones exactly."""
+    rng = np.random.default_rng(7)
+    w1 = rng.integers(-1, 2, size=(3, 3, 4, 32)) / 4.0          # |z1| <= 9, step 1/4
+    w2 = np.zeros((3, 3, 32, 32))
+    w2[1, 1] = np.eye(32)                                        # z2 = a1 + b2
+    w3 = rng.integers(0, 2, size=(3, 3, 32, 4)) / 2.0
+    params = [(w1, rng.integers(-2, 3, 32) / 4.0), (w2, rng.integers(-2, 3, 32) / 4.0),
+              (w3, rng.integers(-2, 3, 4) / 4.0)]
+    x = rng.integers(-1, 2, size=(1, 4, 32, 4)).astype(float)
+    y, _, _ = C.forward(params, x)
+    ys, _ = C.forward_stored(params, x)
+    np.testing.assert_array_equal(y, ys)
+    # generic data: stored variant within BF16 rounding of the FP64 passes
+    params = C.init_params(1)
+    x = rng.normal(size=(2, 8, 32, 4))
+    t = rng.normal(size=(2, 8, 32, 4)) * 0.1
+    l, g = C.loss_and_grads(params, x, t)
+    ls, gs = C.loss_and_grads_stored(params, x, t)
+    assert ls == pytest.approx(l, rel=2e-2)
+    for (gw, gb), (sw, sb) in zip(g, gs):
+        assert np.linalg.norm(sw - gw) < 3e-2 * np.linalg.norm(gw)
+        assert np.linalg.norm(sb - gb) < 3e-2 * np.linalg.norm(gb) + 1e-12
+
+
+def test_flatten_layout_and_round_trip():
+    params = C.init_params(3)
+    v = C.flatten(params)
+    assert v.size == 11588
+    # W1[dy=1][dx=2][ci=3][co=5] sits at ((1*3+2)*4+3)*32+5
+    assert v[((1 * 3 + 2) * 4 + 3) * 32 + 5] == params[0][0][1, 2, 3, 5]
+    assert v[1152 + 7] == params[0][1][7]
+    back = C.unflatten(v)
+    for (w, b), (w2, b2) in zip(params, back):
+        np.testing.assert_array_equal(w, w2)
+        np.testing.assert_array_equal(b, b2)
+
+
+def test_correction_conserves_mass_and_momentum():
+    rng = np.random.default_rng(8)
+    rho = rng.uniform(0.8, 1.2, size=(16, 16))
+    ux, uy = rng.normal(size=(2, 16, 16)) * 0.1
+    th = rng.uniform(0.2, 0.3, size=(16, 16))
+    d = rng.normal(size=(4, 16, 16)) * 0.01
+    r2, u2, v2, t2 = C.apply_correction(rho, ux, uy, th, d)
+    assert r2.sum() == pytest.approx(rho.sum(), rel=1e-14)
+    assert (r2 * u2).sum() == pytest.approx((rho * ux).sum(), abs=1e-12)
+    assert (r2 * v2).sum() == pytest.approx((rho * uy).sum(), abs=1e-12)
+    np.testing.assert_allclose(t2, th + d[3])
+    # zero increment: unchanged state
+    z = C.apply_correction(rho, ux, uy, th, np.zeros((4, 16, 16)))
+    for a, b in zip(z, (rho, ux, uy, th)):
+        np.testing.assert_allclose(a, b, rtol=1e-15, atol=1e-17)
+    # without conservation: plain increments
+    r3, u3, v3, _ = C.apply_correction(rho, ux, uy, th, d, conserve=False)
+    np.testing.assert_allclose(r3, rho + d[0])
+    np.testing.assert_allclose(u3, ux + d[1])
