@@ -198,8 +198,8 @@ int hlbm_batch_status(hlbm_batch *b, int32_t *host_flags, hlbm_stream_t stream);
  * Synchronises `stream`. */
 int hlbm_batch_set_tile(hlbm_batch *b, int32_t tile_w, int32_t tile_h, hlbm_stream_t stream);
 
-/* Time `steps` steps for every tile shape in {64, 128, 256} x {16, 32, 64,
- * 128}, keep the fastest and report it.  Advances the domains; save and load
+/* Time `steps` steps for every tile shape in {64, 128, 256} x {8, 16, 32,
+ * 64, 128}, keep the fastest and report it.  Advances the domains; save and load
  * the state around it to keep them.  Synchronises `stream`. */
 int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, int32_t *host_best_w, int32_t *host_best_h,
                         hlbm_stream_t stream);

@@ -66,6 +66,18 @@ int hlbm_cnn_get_grads(hlbm_cnn *c, float *dst, hlbm_stream_t stream);
  * out_std[4] (std > 0).  Host-side; applies to calls enqueued afterwards. */
 int hlbm_cnn_set_norm(hlbm_cnn *c, const float *host_norm);
 
+/* Bound on the standardised output of hlbm_cnn_forward (and so of the
+ * closure's increments): each channel's CNN output is clamped to
+ * [-clip, clip] before de-standardising; 0 (the default) disables it.
+ * Training (hlbm_cnn_loss_grad) never clamps.  Host-side. */
+int hlbm_cnn_set_output_clip(hlbm_cnn *c, float clip);
+
+/* Inference kernel: enable = 1 (the default) runs the three layers in one
+ * kernel with the activations in LDS whenever nx is a multiple of 64 and no
+ * idx is given; enable = 0 always runs one kernel per layer through the
+ * workspace.  Both give identical results.  Host-side. */
+int hlbm_cnn_set_fused(hlbm_cnn *c, int32_t enable);
+
 /* Inference: y = CNN(x) for `batch` (1..max_batch) fields, written to y in
  * raw units.  x and y must not overlap. */
 int hlbm_cnn_forward(hlbm_cnn *c, const float *x, int64_t x_sstride, int64_t x_cstride,

@@ -93,6 +93,8 @@ def lib():
             "hlbm_cnn_get_params": (ctypes.c_int, [vp, vp, vp]),
             "hlbm_cnn_get_grads": (ctypes.c_int, [vp, vp, vp]),
             "hlbm_cnn_set_norm": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_float)]),
+            "hlbm_cnn_set_output_clip": (ctypes.c_int, [vp, ctypes.c_float]),
+            "hlbm_cnn_set_fused": (ctypes.c_int, [vp, i32]),
             "hlbm_cnn_forward": (ctypes.c_int, [vp, vp, i64, i64, vp, i32, vp, i64, i64, vp]),
             "hlbm_cnn_loss_grad": (ctypes.c_int, [vp, vp, i64, i64, vp, i64, i64, vp, i32, vp,
                                                   vp]),
@@ -356,18 +358,26 @@ class BatchSolver:
         self._leave()
         return self
 
-    def moments(self):
-        """List of per-domain dicts of [ny][nx] tensors (views of one buffer)."""
+    def moments_cat(self, out=None, keys=("rho", "ux", "uy", "s", "theta")):
+        """Concatenated fields of all domains: dict of 1-D tensors.  With
+        ``out`` (a [len(keys)][nodes] tensor) the fields are written there."""
         import torch
         td = self.params[0].torch_dtype
         n = int(self.offsets[-1])
-        cat = {k: torch.empty(n, dtype=td, device=self.device)
-               for k in ("rho", "ux", "uy", "s", "theta")}
+        if out is None:
+            out = torch.empty(len(keys), n, dtype=td, device=self.device)
+        cat = {k: out[j] for j, k in enumerate(keys)}
         self._enter()
-        _check(lib().hlbm_batch_moments(self.h, _ptr(cat["rho"]), _ptr(cat["ux"]),
-                                        _ptr(cat["uy"]), _ptr(cat["s"]), _ptr(cat["theta"]),
-                                        _stream(self.stream)), "hlbm_batch_moments")
+        _check(lib().hlbm_batch_moments(self.h, _ptr(cat.get("rho")), _ptr(cat.get("ux")),
+                                        _ptr(cat.get("uy")), _ptr(cat.get("s")),
+                                        _ptr(cat.get("theta")), _stream(self.stream)),
+               "hlbm_batch_moments")
         self._leave()
+        return cat
+
+    def moments(self):
+        """List of per-domain dicts of [ny][nx] tensors (views of one buffer)."""
+        cat = self.moments_cat()
         out = []
         for k, p in enumerate(self.params):
             a, b = int(self.offsets[k]), int(self.offsets[k + 1])

@@ -12,6 +12,17 @@ from ._lib import HLBM_EINVAL, HlbmError, _check, _ptr, _stream, lib
 N_PARAMS = 11588
 
 
+def _field_strides(t, ny, nx, what):
+    """(sample, channel) strides of a [S][4][ny][nx] float32 tensor whose
+    [ny][nx] planes are contiguous (any sample / channel strides)."""
+    import torch
+    if t.dtype != torch.float32 or t.dim() != 4 or t.shape[1] != 4 or t.shape[2:] != (ny, nx):
+        raise ValueError(f"{what}: expected a float32 [S][4][{ny}][{nx}] tensor")
+    if t.stride(3) != 1 or t.stride(2) != nx:
+        raise ValueError(f"{what}: [ny][nx] planes must be contiguous")
+    return t.stride(0), t.stride(1)
+
+
 def _f32(t, device):
     import torch
     return torch.as_tensor(t).to(device=device, dtype=torch.float32).contiguous()
@@ -40,6 +51,7 @@ class CNN:
                "hlbm_cnn_init")
         self.h = h
         self.norm = np.array([0, 0, 0, 0, 1, 1, 1, 1, 0, 0, 0, 0, 1, 1, 1, 1], np.float32)
+        self.clip = 0.0
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -69,30 +81,39 @@ class CNN:
         _check(lib().hlbm_cnn_set_norm(self.h, arr), "hlbm_cnn_set_norm")
         self.norm = norm
 
-    def _strides(self, sstride, cstride):
-        n = self.ny * self.nx
-        return (4 * n if sstride is None else int(sstride)), (n if cstride is None else int(cstride))
+    def set_output_clip(self, clip):
+        """Clamp the standardised inference output to [-clip, clip] (0: off)."""
+        _check(lib().hlbm_cnn_set_output_clip(self.h, float(clip)), "hlbm_cnn_set_output_clip")
+        self.clip = float(clip)
+
+    def set_fused(self, enable):
+        """Inference in one fused kernel (True, the default) or per layer."""
+        _check(lib().hlbm_cnn_set_fused(self.h, int(bool(enable))), "hlbm_cnn_set_fused")
+
+    def _strides(self, t, sstride, cstride, what="x"):
+        """Explicit strides, or those of a [S][4][ny][nx] tensor."""
+        if sstride is not None and cstride is not None:
+            return int(sstride), int(cstride)
+        return _field_strides(t, self.ny, self.nx, what)
 
     def forward(self, x, batch=None, idx=None, sstride=None, cstride=None, out=None):
         """Raw increments [batch][4][ny][nx] for the fields x."""
         import torch
-        sb, sc = self._strides(sstride, cstride)
-        batch = int(batch if batch is not None else (len(idx) if idx is not None else
-                                                     x.numel() // (4 * self.ny * self.nx)))
+        sb, sc = self._strides(x, sstride, cstride)
+        batch = int(batch if batch is not None else (len(idx) if idx is not None else x.shape[0]))
         if out is None:
             out = torch.empty(batch, 4, self.ny, self.nx, dtype=torch.float32, device=self.device)
-        n = self.ny * self.nx
+        osb, osc = _field_strides(out, self.ny, self.nx, "out")
         _check(lib().hlbm_cnn_forward(self.h, _ptr(x), sb, sc, _ptr(idx), batch, _ptr(out),
-                                      4 * n, n, _stream()), "hlbm_cnn_forward")
+                                      osb, osc, _stream()), "hlbm_cnn_forward")
         return out
 
     def loss_grad(self, x, target, batch=None, idx=None, sstride=None, cstride=None,
                   t_sstride=None, t_cstride=None, loss=None):
         import torch
-        sb, sc = self._strides(sstride, cstride)
-        tsb, tsc = self._strides(t_sstride, t_cstride)
-        batch = int(batch if batch is not None else (len(idx) if idx is not None else
-                                                     x.numel() // (4 * self.ny * self.nx)))
+        sb, sc = self._strides(x, sstride, cstride)
+        tsb, tsc = self._strides(target, t_sstride, t_cstride, "target")
+        batch = int(batch if batch is not None else (len(idx) if idx is not None else x.shape[0]))
         if loss is None:
             loss = torch.empty(1, dtype=torch.float32, device=self.device)
         _check(lib().hlbm_cnn_loss_grad(self.h, _ptr(x), sb, sc, _ptr(target), tsb, tsc,
@@ -106,10 +127,9 @@ class CNN:
     def train_step(self, x, target, lr, batch=None, idx=None, sstride=None, cstride=None,
                    t_sstride=None, t_cstride=None, loss=None):
         import torch
-        sb, sc = self._strides(sstride, cstride)
-        tsb, tsc = self._strides(t_sstride, t_cstride)
-        batch = int(batch if batch is not None else (len(idx) if idx is not None else
-                                                     x.numel() // (4 * self.ny * self.nx)))
+        sb, sc = self._strides(x, sstride, cstride)
+        tsb, tsc = self._strides(target, t_sstride, t_cstride, "target")
+        batch = int(batch if batch is not None else (len(idx) if idx is not None else x.shape[0]))
         if loss is None:
             loss = torch.empty(1, dtype=torch.float32, device=self.device)
         _check(lib().hlbm_cnn_train_step(self.h, _ptr(x), sb, sc, _ptr(target), tsb, tsc,
@@ -124,10 +144,15 @@ def restrict(rho, ux, uy, theta, factor, batch=1, out=None):
     import torch
     ny, nx = rho.shape[-2], rho.shape[-1]
     nyc, nxc = ny // factor, nx // factor
+    for a in (rho, ux, uy, theta):
+        if a.dtype != torch.float32 or not a.is_contiguous() or a.numel() != batch * ny * nx:
+            raise ValueError("fine fields: contiguous float32 [batch][ny][nx]")
     if out is None:
         out = torch.empty(batch, 4, nyc, nxc, dtype=torch.float32, device=rho.device)
-    n = nyc * nxc
+    if out.shape[0] != batch:
+        raise ValueError("out: one entry per batch member")
+    osb, osc = _field_strides(out, nyc, nxc, "out")
     _check(lib().hlbm_restrict(_ptr(rho), _ptr(ux), _ptr(uy), _ptr(theta), int(batch), int(ny),
-                               int(nx), int(factor), _ptr(out), 4 * n, n, _stream()),
+                               int(nx), int(factor), _ptr(out), osb, osc, _stream()),
            "hlbm_restrict")
     return out

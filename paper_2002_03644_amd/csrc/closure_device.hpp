@@ -123,5 +123,35 @@ __global__ __launch_bounds__(kCorrThreads) void k_corr_apply(CorrArgs a) {
   }
 }
 
+// Macroscopic fields of every domain of a batch in one launch: workgroup
+// column y = domain, fields concatenated at foffs[k] (as k_moments per domain).
+struct BatchFieldArgs {
+  const DomainArgs *doms;
+  const long long *offs, *foffs;
+  const real *state;
+  real *rho, *ux, *uy, *s, *theta;
+};
+
+__global__ __launch_bounds__(256) void k_batch_moments(BatchFieldArgs a) {
+  const int k = blockIdx.y;
+  const DomainArgs &d = a.doms[k];
+  const long long n = (long long)d.nx * d.ny, P = d.plane;
+  const real *st = a.state + a.offs[k];
+  const long long fo = a.foffs[k];
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    real F[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) F[q] = st[q * P + i];
+    const real sv = st[9 * P + i];
+    const NodeMoments m = node_moments(F, d);
+    if (a.rho) a.rho[fo + i] = m.rho;
+    if (a.ux) a.ux[fo + i] = m.jx / m.rho;
+    if (a.uy) a.uy[fo + i] = m.jy / m.rho;
+    if (a.s) a.s[fo + i] = sv + d.s_ref;
+    if (a.theta) a.theta[fo + i] = node_theta(m.rho, sv, d);
+  }
+}
+
 }  // namespace HLBM_NS
 }  // namespace hlbm

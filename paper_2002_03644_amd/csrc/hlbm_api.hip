@@ -350,7 +350,8 @@ struct hlbm_batch {
   std::vector<long long> field_offs;  // offset of each domain in the concatenated fields
   std::vector<long long> state_elems; // ten planes of each domain
   char *ws = nullptr;
-  size_t off_buf1 = 0, off_doms = 0, off_offs = 0, off_items = 0, off_stat = 0, off_corr = 0;
+  size_t off_buf1 = 0, off_doms = 0, off_offs = 0, off_foffs = 0, off_items = 0, off_stat = 0;
+  size_t off_corr = 0;
   size_t total = 0;
   size_t state_bytes = 0;             // one buffer
   int max_items = 0, nitems = 0, tile_w = 128, tile_h = 32, grid = 1, cur = 0, ncu = 1;
@@ -358,7 +359,7 @@ struct hlbm_batch {
   hipGraphExec_t graph = nullptr;
   int graph_cur = -1;
   hipGraphExec_t cgraph = nullptr;    // captured corrected steps (hlbm_closure_step)
-  int cgraph_cur = -1, cgraph_conserve = -1;
+  int cgraph_cur = -1, cgraph_conserve = -1, cgraph_version = -1;
   const hlbm_cnn *cgraph_net = nullptr;
 };
 
@@ -414,7 +415,8 @@ void batch_layout(hlbm_batch *b) {
   b->off_doms = 2 * b->state_bytes;
   const size_t dbytes = std::max(hlbm::f32::domain_args_bytes(), hlbm::f64::domain_args_bytes());
   b->off_offs = b->off_doms + round_up(dbytes * b->count, kAlign);
-  b->off_items = b->off_offs + round_up(sizeof(long long) * b->count, kAlign);
+  b->off_foffs = b->off_offs + round_up(sizeof(long long) * b->count, kAlign);
+  b->off_items = b->off_foffs + round_up(sizeof(long long) * b->count, kAlign);
   b->off_stat = b->off_items + round_up(sizeof(int) * 4 * (size_t)b->max_items, kAlign);
   b->off_corr = b->off_stat + round_up(sizeof(unsigned) * b->count, kAlign);
   b->total = b->off_corr + round_up(std::max(hlbm::f32::correct_partials_bytes(b->count),
@@ -524,6 +526,9 @@ int hlbm_batch_init(hlbm_batch **out, const hlbm_params *params, int32_t count, 
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->ws + b->off_offs, b->offs.data(), sizeof(long long) * count,
                        hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->ws + b->off_foffs, b->field_offs.data(), sizeof(long long) * count,
+                       hipMemcpyHostToDevice, st);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_clear_words, dim3((count + 255) / 256), dim3(256), 0, st,
                        (unsigned *)(b->ws + b->off_stat), count);
@@ -593,19 +598,19 @@ int hlbm_batch_moments(hlbm_batch *b, void *rho, void *ux, void *uy, void *s, vo
                        hlbm_stream_t stream) {
   if (!b) return HLBM_EINVAL;
   hipStream_t st = (hipStream_t)stream;
-  const size_t el = elem_size(b->dtype);
-  auto at = [&](void *p, long long fo) { return p ? (void *)((char *)p + fo * el) : nullptr; };
-  for (int k = 0; k < b->count; ++k) {
-    const long long fo = b->field_offs[k];
-    const char *state = b->ws + (b->cur ? b->off_buf1 : 0) + b->offs[k] * el;
-    hipError_t e = b->dtype == HLBM_F64
-                       ? hlbm::f64::moments(b->doms[k], state, at(rho, fo), at(ux, fo), at(uy, fo),
-                                            at(s, fo), at(theta, fo), st)
-                       : hlbm::f32::moments(b->doms[k], state, at(rho, fo), at(ux, fo), at(uy, fo),
-                                            at(s, fo), at(theta, fo), st);
-    if (e != hipSuccess) return HLBM_EHIP;
-  }
-  return HLBM_OK;
+  const char *state = b->ws + (b->cur ? b->off_buf1 : 0);
+  long long maxn = 0;
+  for (int k = 0; k < b->count; ++k)
+    maxn = std::max(maxn, (long long)b->params[k].nx * b->params[k].ny);
+  const long long *offs = (const long long *)(b->ws + b->off_offs);
+  const long long *foffs = (const long long *)(b->ws + b->off_foffs);
+  const void *doms = b->ws + b->off_doms;
+  hipError_t e = b->dtype == HLBM_F64
+                     ? hlbm::f64::batch_moments(doms, offs, foffs, b->count, maxn, state, rho, ux,
+                                                uy, s, theta, st)
+                     : hlbm::f32::batch_moments(doms, offs, foffs, b->count, maxn, state, rho, ux,
+                                                uy, s, theta, st);
+  return hip_status(e);
 }
 
 int hlbm_batch_status(hlbm_batch *b, int32_t *host_flags, hlbm_stream_t stream) {
@@ -635,7 +640,7 @@ int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, int32_t *host_best_w, int3
                         hlbm_stream_t stream) {
   if (!b || steps < 1) return HLBM_EINVAL;
   hipStream_t st = (hipStream_t)stream;
-  const int hs[4] = {16, 32, 64, 128};
+  const int hs[5] = {8, 16, 32, 64, 128};
   float best = 1e30f;
   int bw = b->tile_w, bh = b->tile_h;
   hipEvent_t e0, e1;
@@ -764,7 +769,7 @@ int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t nsteps, int32_t conser
   int n = nsteps;
   if (use_graph && n >= 2) {
     if (!b->cgraph || b->cgraph_cur != b->cur || b->cgraph_net != c ||
-        b->cgraph_conserve != conserve) {
+        b->cgraph_conserve != conserve || b->cgraph_version != hlbm_cnn_version(c)) {
       if (b->cgraph) {
         hipGraphExecDestroy(b->cgraph);
         b->cgraph = nullptr;
@@ -790,6 +795,7 @@ int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t nsteps, int32_t conser
       b->cgraph_cur = b->cur;
       b->cgraph_net = c;
       b->cgraph_conserve = conserve;
+      b->cgraph_version = hlbm_cnn_version(c);
     }
     for (; n >= 2; n -= 2) {
       if (hipGraphLaunch(b->cgraph, st) != hipSuccess) return HLBM_EHIP;

@@ -183,6 +183,25 @@ hipError_t correct(const void *doms, const long long *offs, int count, long long
   return hipGetLastError();
 }
 
+hipError_t batch_moments(const void *doms, const long long *offs, const long long *foffs,
+                         int count, long long maxn, const void *state, void *rho, void *ux,
+                         void *uy, void *s, void *theta, hipStream_t st) {
+  BatchFieldArgs a;
+  a.doms = (const DomainArgs *)doms;
+  a.offs = offs;
+  a.foffs = foffs;
+  a.state = (const real *)state;
+  a.rho = (real *)rho;
+  a.ux = (real *)ux;
+  a.uy = (real *)uy;
+  a.s = (real *)s;
+  a.theta = (real *)theta;
+  const long long per = (maxn + 255) / 256;
+  const int gx = (int)(per < 128 ? per : 128);
+  hipLaunchKernelGGL(k_batch_moments, dim3(gx, count), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 size_t correct_partials_bytes(int count) {
   return sizeof(double) * kCorrParts * kCorrVals * (size_t)count;
 }

@@ -46,6 +46,9 @@ struct TileShape {
                      void *state, const float *x, const float *dl, double *partials,        \
                      int conserve, hipStream_t st);                                         \
   size_t correct_partials_bytes(int count);                                                 \
+  hipError_t batch_moments(const void *doms, const long long *offs, const long long *foffs, \
+                           int count, long long maxn, const void *state, void *rho, void *ux,  \
+                           void *uy, void *s, void *theta, hipStream_t st);                  \
   }
 
 HLBM_DECLARE_LAUNCHERS(f32)

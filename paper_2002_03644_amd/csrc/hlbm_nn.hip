@@ -45,6 +45,9 @@ struct hlbm_cnn {
   double *lpart = nullptr;
   size_t total = 0;
   float norm[16];
+  float clip = 0.f;
+  int fused = 1;            // inference through k_cnn_fused where the size allows
+  int version = 0;          // bumped when launch arguments (norm, clip) change
   long long adam_t = 0;
 };
 
@@ -135,6 +138,7 @@ hipError_t conv(hlbm_cnn *c, int B, const bf16 *in, int pk, const float *bias, c
     a.om[k] = c->norm[8 + k];
     a.os[k] = c->norm[12 + k];
   }
+  a.clip = c->clip;
   const long long units = (long long)B * a.nsx * a.nry;
   hipLaunchKernelGGL((k_conv<CIN, NB, EPI>), dim3((units + kConvWaves - 1) / kConvWaves),
                      dim3(64 * kConvWaves), 0, st, a);
@@ -189,6 +193,45 @@ hipError_t hidden(hlbm_cnn *c, int B, hipStream_t st) {
   return e;
 }
 
+// rows per workgroup of the fused kernel: a divisor of H (a multiple of 4),
+// halved until there is one workgroup per compute unit; 0 if the width
+// does not tile by 64 columns
+int fused_rows(int B, int H, int W) {
+  if (W % kFuseOut) return 0;
+  int R = kFuseMaxRows;
+  while (R > 4 && (H % R != 0 || (long long)B * (W / kFuseOut) * (H / R) < 256)) R /= 2;
+  return H % R == 0 ? R : 0;
+}
+
+hipError_t fused_forward(hlbm_cnn *c, const float *x, long long sb, long long sc, int B, float *y,
+                         long long osb, long long osc, int R, hipStream_t st) {
+  FusedArgs a;
+  a.x = x;
+  a.sb = sb;
+  a.sc = sc;
+  a.wp = (const bf16x8 *)c->packed;
+  a.b1 = c->params + kOffB1;
+  a.b2 = c->params + kOffB2;
+  a.b3 = c->params + kOffB3;
+  a.y = y;
+  a.osb = osb;
+  a.osc = osc;
+  a.H = c->H;
+  a.W = c->W;
+  a.rows = R;
+  a.ncb = c->W / kFuseOut;
+  a.nrb = c->H / R;
+  for (int k = 0; k < 4; ++k) {
+    a.mean[k] = c->norm[k];
+    a.inv_std[k] = 1.f / c->norm[4 + k];
+    a.om[k] = c->norm[8 + k];
+    a.os[k] = c->norm[12 + k];
+  }
+  a.clip = c->clip;
+  hipLaunchKernelGGL(k_cnn_fused, dim3(B * a.ncb * a.nrb), dim3(64 * kFuseWaves), 0, st, a);
+  return hipGetLastError();
+}
+
 bool args_ok(const hlbm_cnn *c, const float *x, int32_t B) {
   return c && x && B >= 1 && B <= c->maxb;
 }
@@ -200,6 +243,7 @@ float *hlbm_cnn_io(hlbm_cnn *c, int which) { return which ? c->io_d : c->io_x; }
 int hlbm_cnn_max_batch(const hlbm_cnn *c) { return c->maxb; }
 int hlbm_cnn_ny(const hlbm_cnn *c) { return c->H; }
 int hlbm_cnn_nx(const hlbm_cnn *c) { return c->W; }
+int hlbm_cnn_version(const hlbm_cnn *c) { return c->version; }
 
 extern "C" {
 
@@ -279,6 +323,21 @@ int hlbm_cnn_set_norm(hlbm_cnn *c, const float *host_norm) {
   for (int k = 0; k < 4; ++k)
     if (!(host_norm[4 + k] > 0.f) || !(host_norm[12 + k] > 0.f)) return HLBM_EINVAL;
   std::copy(host_norm, host_norm + 16, c->norm);
+  ++c->version;
+  return HLBM_OK;
+}
+
+int hlbm_cnn_set_output_clip(hlbm_cnn *c, float clip) {
+  if (!c || !(clip >= 0.f) || !std::isfinite(clip)) return HLBM_EINVAL;
+  c->clip = clip;
+  ++c->version;
+  return HLBM_OK;
+}
+
+int hlbm_cnn_set_fused(hlbm_cnn *c, int32_t enable) {
+  if (!c) return HLBM_EINVAL;
+  c->fused = enable ? 1 : 0;
+  ++c->version;
   return HLBM_OK;
 }
 
@@ -287,6 +346,10 @@ int hlbm_cnn_forward(hlbm_cnn *c, const float *x, int64_t x_sstride, int64_t x_c
                      int64_t y_cstride, hlbm_stream_t stream) {
   if (!args_ok(c, x, batch) || !y || y_sstride <= 0 || y_cstride <= 0) return HLBM_EINVAL;
   hipStream_t st = (hipStream_t)stream;
+  const int R = fused_rows(batch, c->H, c->W);
+  if (c->fused && R > 0 && !idx)
+    return hip_status(fused_forward(c, x, x_sstride, x_cstride, batch, y, y_sstride, y_cstride,
+                                    R, st));
   hipError_t e = prep(c, x, x_sstride, x_cstride, idx, batch, st);
   if (e == hipSuccess) e = hidden(c, batch, st);
   if (e == hipSuccess)
@@ -326,7 +389,7 @@ int hlbm_cnn_loss_grad(hlbm_cnn *c, const float *x, int64_t x_sstride, int64_t x
   const int parts = std::min(kLossParts, grid_for((long long)B * c->npix, kLossThreads));
   hipLaunchKernelGGL(k_loss, dim3(parts), dim3(kLossThreads), 0, st, la);
   if (loss)
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, (const double *)c->lpart, parts,
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, (const double *)c->lpart, parts,
                        1.0 / nel, loss);
   e = hipGetLastError();
   // layer 3: weights from (a2, g3); back to layer 2 through the ReLU of a2

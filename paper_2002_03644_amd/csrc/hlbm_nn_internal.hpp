@@ -9,3 +9,6 @@ float *hlbm_cnn_io(hlbm_cnn *c, int which);
 int hlbm_cnn_max_batch(const hlbm_cnn *c);
 int hlbm_cnn_ny(const hlbm_cnn *c);
 int hlbm_cnn_nx(const hlbm_cnn *c);
+// changes whenever values captured into launch arguments (standardisation,
+// output clamp) change, so captured graphs can be rebuilt
+int hlbm_cnn_version(const hlbm_cnn *c);

@@ -145,7 +145,8 @@ struct ConvArgs {
   float *outf;             // kEpiOut: standardised NHWC4, or raw planes
   long long osb, osc;      // kEpiOut raw planes: sample / channel strides; osb 0: NHWC4
   int B, H, W, rows, nsx, nry;
-  float os[4], om[4];      // kEpiOut raw: y = y_std * os + om
+  float os[4], om[4];      // kEpiOut raw: y = clamp(y_std, -clip, clip) * os + om
+  float clip;              // kEpiOut raw: bound on |y_std| (0: none)
 };
 
 // One wave computes a 16-pixel wide strip of `rows` output rows.  For 32
@@ -204,7 +205,10 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         } else {
           const long long i = (long long)yo * W + x0 + n;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) a.outf[b * a.osb + r * a.osc + i] = acc[0][r] * a.os[r] + a.om[r];
+          for (int r = 0; r < 4; ++r) {
+            const float ys = a.clip > 0.f ? fminf(fmaxf(acc[0][r], -a.clip), a.clip) : acc[0][r];
+            a.outf[b * a.osb + r * a.osc + i] = ys * a.os[r] + a.om[r];
+          }
         }
       }
     }
@@ -282,6 +286,160 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma(wf[j][nb], bv, acc[nb]);
       }
       epilogue(acc, yo);
+    }
+  }
+}
+
+// ------------------------------------------------------- fused inference
+// The three layers in one kernel, activations kept in LDS.  A workgroup of
+// five waves owns 64 output columns of `rows` rows of one image.  It works on
+// an 80-column region (the 64 columns plus 8 on each side, one 16-pixel strip
+// per wave); a layer's value at the region's outermost column is wrong (its
+// neighbour outside the region is replaced by the edge column), and that
+// error moves inwards one column per layer, so after three layers the 64
+// middle columns are exact.  The standardised input rows y0-3 .. y0+rows+2 are staged in LDS
+// first, so the row loop issues no global loads (and never waits on its own
+// output stores).  Layer rows stream through four-row rings: at step j the
+// workgroup computes layer-1 row y0+j-3, layer-2 row y0+j-5 and output row
+// y0+j-7, each from rows the previous three steps completed, with one
+// barrier per step.  The arithmetic (tap order, FP32 accumulation, BF16
+// rounding points) is that of k_prep and k_conv, so both paths give
+// identical results.
+constexpr int kFuseCols = 80, kFuseOut = 64, kFuseWaves = 5, kRing = 4;
+constexpr int kFuseMaxRows = 32;
+// LDS pixel stride of the layer rings in BF16 elements: 32 channels padded to
+// 40 (80 bytes), which spreads the 16-byte reads of a fragment's 16 pixels
+// over the LDS banks
+constexpr int kPixPad = 40;
+
+struct FusedArgs {
+  const float *x;
+  long long sb, sc;
+  const bf16x8 *wp;        // all packed fragments
+  const float *b1, *b2, *b3;
+  float *y;
+  long long osb, osc;
+  int H, W, rows, ncb, nrb;
+  float mean[4], inv_std[4], os[4], om[4], clip;
+};
+
+__global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
+  __shared__ __attribute__((aligned(16))) bf16 in_tile[kFuseMaxRows + 6][kFuseCols][4];
+  __shared__ __attribute__((aligned(16))) bf16 l1_ring[kRing][kFuseCols][kPixPad];
+  __shared__ __attribute__((aligned(16))) bf16 l2_ring[kRing][kFuseCols][kPixPad];
+  const int tid = threadIdx.x, lane = tid & 63, s = tid >> 6;
+  const int n = lane & 15, g = lane >> 4;
+  const int cb = blockIdx.x % a.ncb;
+  const int rest = blockIdx.x / a.ncb;
+  const int rb = rest % a.nrb, b = rest / a.nrb;
+  const int H = a.H, W = a.W, R = a.rows;
+  const int x0 = cb * kFuseOut, y0 = rb * R;
+
+  // stage the standardised input: tile row q holds image row y0 - 3 + q
+  {
+    const int lc = tid % kFuseCols, lch = tid / kFuseCols;   // 320 threads = 80 x 4
+    int gx = x0 - 8 + lc;
+    gx = gx < 0 ? gx + W : (gx >= W ? gx - W : gx);
+    const float *src = a.x + b * a.sb + lch * a.sc + gx;
+    const float mean = a.mean[lch], inv = a.inv_std[lch];
+    for (int q = 0; q < R + 6; ++q) {
+      int yy = (y0 - 3 + q) % H;
+      yy = yy < 0 ? yy + H : yy;
+      in_tile[q][lc][lch] = (bf16)((src[(long long)yy * W] - mean) * inv);
+    }
+  }
+
+  bf16x8 w1[2][2], w2[9][2], w3[9];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) w1[j][nb] = a.wp[kPk1 + (j * 2 + nb) * 64 + lane];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) w2[t][nb] = a.wp[kPk2 + (t * 2 + nb) * 64 + lane];
+    w3[t] = a.wp[kPk3 + t * 64 + lane];
+  }
+  f32x4 bias1[2], bias2[2], bias3;
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      bias1[nb][r] = a.b1[16 * nb + 4 * g + r];
+      bias2[nb][r] = a.b2[16 * nb + 4 * g + r];
+    }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) bias3[r] = (4 * g + r < kOut) ? a.b3[4 * g + r] : 0.f;
+
+  const int col = s * 16 + n;                          // this lane's region column
+  // a neighbour outside the region reads the edge column instead: the value
+  // is wrong there either way and only the middle 64 columns are kept
+  auto clampc = [](int c) { return c < 0 ? 0 : (c >= kFuseCols ? kFuseCols - 1 : c); };
+  for (int j = 1; j <= R + 6; ++j) {
+    __syncthreads();
+    // layer rows completed at steps j-3, j-2, j-1 sit in ring slots
+    // (j+5+dy) & 3 for dy = 0, 1, 2; input row y0+j-4+dy is tile row j-1+dy
+    if (j <= R + 4) {                    // layer 1, row y0 + j - 3
+      f32x4 acc[2] = {bias1[0], bias1[1]};
+      bf16x4 v[2][2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int t = 8 * h + 2 * g + e;
+          const int tt = t < 9 ? t : 8;
+          const int dy = tt / 3, dx = tt - 3 * (tt / 3);
+          v[h][e] = *(const bf16x4 *)&in_tile[j - 1 + dy][clampc(col + dx - 1)][0];
+          if (t >= 9) v[h][e] = bf16x4{(bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f};
+        }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bf16x8 bv = __builtin_shufflevector(v[h][0], v[h][1], 0, 1, 2, 3, 4, 5, 6, 7);
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) acc[nb] = mfma(w1[h][nb], bv, acc[nb]);
+      }
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        bf16x4 o;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[r] = (bf16)fmaxf(acc[nb][r], 0.f);
+        *(bf16x4 *)&l1_ring[j & 3][col][16 * nb + 4 * g] = o;
+      }
+    }
+    if (j >= 4 && j <= R + 5) {          // layer 2, row y0 + j - 5
+      f32x4 acc[2] = {bias2[0], bias2[1]};
+      bf16x8 bv[9];
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+        bv[t] = *(const bf16x8 *)&l1_ring[(j + 5 + t / 3) & 3][clampc(col + t % 3 - 1)][8 * g];
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) acc[nb] = mfma(w2[t][nb], bv[t], acc[nb]);
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        bf16x4 o;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[r] = (bf16)fmaxf(acc[nb][r], 0.f);
+        *(bf16x4 *)&l2_ring[j & 3][col][16 * nb + 4 * g] = o;
+      }
+    }
+    if (j >= 7) {                        // output, row y0 + j - 7
+      f32x4 acc = bias3;
+      bf16x8 bv[9];
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+        bv[t] = *(const bf16x8 *)&l2_ring[(j + 5 + t / 3) & 3][clampc(col + t % 3 - 1)][8 * g];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) acc = mfma(w3[t], bv[t], acc);
+      if (g == 0 && col >= 8 && col < 8 + kFuseOut) {
+        const long long i = (long long)(y0 + j - 7) * W + x0 + col - 8;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float ys = a.clip > 0.f ? fminf(fmaxf(acc[r], -a.clip), a.clip) : acc[r];
+          a.y[b * a.osb + r * a.osc + i] = ys * a.os[r] + a.om[r];
+        }
+      }
     }
   }
 }
@@ -488,11 +646,16 @@ __global__ __launch_bounds__(kLossThreads) void k_loss(LossArgs a) {
   }
 }
 
-__global__ void k_loss_final(const double *partials, int nparts, double inv_n, float *loss) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(256) void k_loss_final(const double *partials, int nparts,
+                                                    double inv_n, float *loss) {
+  __shared__ double red[4];
   double s = 0.0;
-  for (int k = 0; k < nparts; ++k) s += partials[k];
-  *loss = (float)(s * inv_n);
+  for (int k = threadIdx.x; k < nparts; k += 256) s += partials[k];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *loss = (float)(((red[0] + red[1]) + (red[2] + red[3])) * inv_n);
 }
 
 // ---------------------------------------------------------------- Adam

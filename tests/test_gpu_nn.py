@@ -134,8 +134,8 @@ def test_training_reduces_loss():
     xs = standardise(x, NORM[0], NORM[1])
     teacher = rand_params(11)
     yt, _, _ = C.forward(teacher, xs)
-    t = (yt.transpose(0, 3, 1, 2) * NORM[3][None, :, None, None]
-         + NORM[2][None, :, None, None]).astype(np.float32)
+    t = np.ascontiguousarray((yt.transpose(0, 3, 1, 2) * NORM[3][None, :, None, None]
+                              + NORM[2][None, :, None, None]).astype(np.float32))
     net = make_net(B, H, W, C.init_params(12))
     xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
     first = float(net.loss_grad(xd, td).item())
@@ -257,3 +257,28 @@ def test_closure_step_graph_equals_eager_and_manual_sequence():
         assert torch.equal(ma, mm), rep
         assert torch.isfinite(ma).all()
     assert A.steps == E.steps == 12
+
+
+@pytest.mark.parametrize("B,H,W", [(3, 12, 64), (2, 256, 256), (1, 36, 128), (5, 8, 192)])
+def test_fused_inference_equals_layer_kernels(B, H, W):
+    """The one-kernel inference (activations in LDS) and the per-layer
+    kernels share every rounding point, so they agree bit for bit; the
+    clamp bounds the standardised output."""
+    params = rand_params(21)
+    x, _ = fields(B, H, W, 22)
+    xd = torch.from_numpy(x).cuda()
+    net = make_net(B, H, W, params)
+    y_fused = net.forward(xd).clone()
+    net.set_fused(False)
+    y_layer = net.forward(xd)
+    assert torch.equal(y_fused, y_layer)
+    ys, _ = C.forward_stored(params, standardise(x, NORM[0], NORM[1]))
+    ys = ys.transpose(0, 3, 1, 2)
+    for clip in (0.5, 2.0):
+        net.set_output_clip(clip)
+        for fused in (True, False):
+            net.set_fused(fused)
+            y = net.forward(xd).cpu().numpy().astype(np.float64)
+            want = np.clip(ys, -clip, clip) * NORM[3][None, :, None, None] + NORM[2][None, :, None, None]
+            err = np.abs(y - want).max(axis=(0, 2, 3)) / NORM[3]
+            assert (err < 2e-2 * clip).all(), (clip, fused, err)
