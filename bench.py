@@ -7,8 +7,12 @@ storage.  One step = one launch of the fused step kernel over the whole grid
 (collision, correction term, streaming and entropy update).
 
 Prints ONE JSON line: MLUPS (million lattice updates per second), the HBM
-roofline of the step kernel, and the FP64 CPU oracle timed on a bounded
-sample of the same workload on the host cores.
+roofline of the step kernel, the FP64 CPU oracle timed on a bounded sample of
+the same workload on the host cores, and (second part of the metric) the
+learned closure: a coarse 256^2 HLBM corrected by the BF16-MFMA network,
+trained on the GPU on 4x-restricted 1024^2 runs, against the plain ladder
+256^2 .. 1024^2 -- wall time of the plain run that reaches the learned run's
+density error, divided by the learned run's wall time.
 """
 from __future__ import annotations
 
@@ -83,12 +87,16 @@ def main():
     ap.add_argument("--tile-w", type=int, default=0)
     ap.add_argument("--tile-h", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-closure part (training + evaluation, about a minute)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 2 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", default="turbulence8192", choices=["turbulence8192", "batch256"],
+    ap.add_argument("--workload", default="turbulence8192",
+                    choices=["turbulence8192", "batch256", "closure"],
                     help="batch256: the 256-domain batch (one persistent launch per step, "
                          "graph-replayed), reported as aggregate MLUPS of the domains still "
-                         "active at the end")
+                         "active at the end; closure: the corrected coarse step of the "
+                         "learned closure (8 x 256^2) and the network's training step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -96,6 +104,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch256":
         return bench_batch(args)
+    if args.workload == "closure":
+        return bench_closure(args)
 
     import numpy as np
     import torch
@@ -153,6 +163,8 @@ def main():
 
     del S
     torch.cuda.empty_cache()
+    learned = None if args.no_learned else learned_closure()
+    torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -167,7 +179,108 @@ def main():
                       "nx": n, "ny": n, "global_batch": 1, "parallelism": "none",
                       "tile_w": params.tile_w or "auto", "tile_h": params.tile_h or "auto",
                       "status_after": int(code)},
-           "roofline": roofline, "cpu_baseline": cpu}
+           "roofline": roofline, "cpu_baseline": cpu, "learned_closure": learned}
+    print(json.dumps(out), flush=True)
+
+
+def learned_closure():
+    """Train the closure on 64 seeds, evaluate on 8 held-out seeds (all on the
+    GPU); report the time at equal density error and the two targets."""
+    import torch
+
+    from paper_2002_03644_amd import learned as L
+    setup = L.ClosureSetup()
+    say = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    t0 = time.perf_counter()
+    net, rec = L.fit(setup, steps=10000, rollout_steps=0, clip=4.0, log=say)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t0
+    ev = L.evaluate(net, setup)
+    nc, nf = setup.coarse_n, setup.fine_n
+    ratio = ev.time_at_equal_error()
+    say(f"[bench] learned closure: e {ev.e_learned:.4f} vs plain {ev.e_plain}, "
+        f"t {ev.t_learned * 1e3:.1f} ms vs {ev.t_plain}")
+    return {"metric": "learned-vs-plain time at equal density L2 error",
+            "value": None if ratio is None else round(ratio, 3), "unit": "x",
+            "higher_is_better": True,
+            "n_equal_error": None if ev.n_equal_error() is None else round(ev.n_equal_error(), 1),
+            "e_learned": round(ev.e_learned, 5),
+            "e_plain": {str(k): round(v, 5) for k, v in sorted(ev.e_plain.items())},
+            "t_learned_ms": round(ev.t_learned * 1e3, 3),
+            "t_plain_ms": {str(k): round(v * 1e3, 3) for k, v in sorted(ev.t_plain.items())},
+            "speedup_vs_fine": round(ev.t_plain[nf] / ev.t_learned, 3),
+            "target_error_within_2x_plain512": bool(ev.e_learned <= 2 * ev.e_plain[512]),
+            "target_10x_faster_than_fine": bool(ev.t_learned <= ev.t_plain[nf] / 10),
+            "diverged": {str(k): v for k, v in ev.diverged.items()},
+            "train": {"pairs": rec["pairs"], "adam_steps": 10000, "batch": 16,
+                      "final_loss": round(rec["loss_phase1"][-1][1], 5), "fit_s": round(fit_s, 1)},
+            "workload": f"decaying turbulence, Ma_t {setup.mach_range[0]}-{setup.mach_range[1]}, "
+                        f"fine {nf}^2 (mu {setup.mu_fine}) restricted {setup.factor}x to {nc}^2; "
+                        f"train seeds {len(setup.train_seeds)}, eval seeds "
+                        f"{len(setup.eval_seeds)} batched, {setup.coarse_steps} coarse steps, "
+                        "error = ||rho - rho_judge|| / ||rho_judge - mean|| over checkpoints "
+                        f"{list(setup.checkpoints)}, times hipGraph-replayed"}
+
+
+def bench_closure(args):
+    """Corrected coarse steps of 8 periodic 256^2 domains (one HLBM step, the
+    moments, the fused network and the correction per step, graph-replayed)
+    and training steps of the network on batches of 16 fields; untrained
+    network (the timing does not depend on the weights)."""
+    import numpy as np
+    import torch
+
+    from paper_2002_03644_amd import CNN, BatchSolver
+    from paper_2002_03644_amd import learned as L
+    setup = L.ClosureSetup()
+    nc = setup.coarse_n
+    seeds = list(setup.eval_seeds)
+    fields, params = [], []
+    for s_ in seeds:
+        r, u, v, t = L.fine_initial(s_, setup)
+        f = setup.factor
+        fields.append(tuple(np.ascontiguousarray(a[::f, ::f]) for a in (r, u, v, t)))
+        params.append(L._params(nc, setup.mu_coarse, float(t[0, 0]), setup))
+    B = BatchSolver(params, fields)
+    tw, th = B.autotune(steps=5)
+    net = CNN(len(seeds), nc, nc, L.initial_params(0))
+    net.set_norm(np.array([1, 0, 0, 0.2], np.float32), np.array([0.1, 0.1, 0.1, 0.01], np.float32),
+                 np.zeros(4, np.float32), np.array([1e-3, 1e-3, 1e-3, 1e-4], np.float32))
+    net.set_output_clip(4.0)
+
+    def timed(fn, stream):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    B.closure_step(net, max(2, args.warmup), graph=True)
+    ms_c = timed(lambda: B.closure_step(net, args.steps, graph=True), B.stream)
+    B.step(max(2, args.warmup), graph=True)
+    ms_p = timed(lambda: B.step(args.steps, graph=True), B.stream)
+    Y = torch.randn(64, 4, nc, nc, device="cuda")
+    D = torch.randn(64, 4, nc, nc, device="cuda")
+    trn = CNN(16, nc, nc, L.initial_params(0))
+    idx = torch.arange(16, dtype=torch.int32, device="cuda")
+    nt = max(10, args.steps // 10)
+    trn.train_step(Y, D, 1e-3, idx=idx)
+    ms_t = timed(lambda: [trn.train_step(Y, D, 1e-3, idx=idx) for _ in range(nt)],
+                 torch.cuda.current_stream())
+    fwd_flop = 2.0 * 65536 * 9 * (4 * 32 + 32 * 32 + 32 * 4)
+    out = {"metric": "corrected coarse step time (8 x 256^2)",
+           "value": round(ms_c / args.steps * 1e3, 2), "unit": "us/step", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms_c / args.steps, 5), "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "8 periodic 256^2 turbulence domains, learned closure",
+                      "tile_w": tw, "tile_h": th},
+           "plain_step_us": round(ms_p / args.steps * 1e3, 2),
+           "train_step_us_batch16": round(ms_t / nt * 1e3, 1),
+           "network_flop_per_field": fwd_flop,
+           "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
 
