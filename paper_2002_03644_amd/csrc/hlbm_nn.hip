@@ -194,12 +194,12 @@ hipError_t hidden(hlbm_cnn *c, int B, hipStream_t st) {
 }
 
 // rows per workgroup of the fused kernel: a divisor of H (a multiple of 4),
-// halved until there is one workgroup per compute unit; 0 if the width
+// halved until there are two workgroups per compute unit; 0 if the width
 // does not tile by 64 columns
 int fused_rows(int B, int H, int W) {
   if (W % kFuseOut) return 0;
   int R = kFuseMaxRows;
-  while (R > 4 && (H % R != 0 || (long long)B * (W / kFuseOut) * (H / R) < 256)) R /= 2;
+  while (R > 4 && (H % R != 0 || (long long)B * (W / kFuseOut) * (H / R) < 512)) R /= 2;
   return H % R == 0 ? R : 0;
 }
 

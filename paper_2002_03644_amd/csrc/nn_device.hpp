@@ -291,21 +291,26 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
 }
 
 // ------------------------------------------------------- fused inference
-// The three layers in one kernel, activations kept in LDS.  A workgroup of
-// five waves owns 64 output columns of `rows` rows of one image.  It works on
-// an 80-column region (the 64 columns plus 8 on each side, one 16-pixel strip
-// per wave); a layer's value at the region's outermost column is wrong (its
-// neighbour outside the region is replaced by the edge column), and that
-// error moves inwards one column per layer, so after three layers the 64
-// middle columns are exact.  The standardised input rows y0-3 .. y0+rows+2 are staged in LDS
-// first, so the row loop issues no global loads (and never waits on its own
-// output stores).  Layer rows stream through four-row rings: at step j the
-// workgroup computes layer-1 row y0+j-3, layer-2 row y0+j-5 and output row
-// y0+j-7, each from rows the previous three steps completed, with one
-// barrier per step.  The arithmetic (tap order, FP32 accumulation, BF16
-// rounding points) is that of k_prep and k_conv, so both paths give
-// identical results.
-constexpr int kFuseCols = 80, kFuseOut = 64, kFuseWaves = 5, kRing = 4;
+// The three layers in one kernel, activations kept in LDS.  A workgroup owns
+// 64 output columns of `rows` rows of one image and works on an 80-column
+// region (the 64 columns plus 8 on each side).  Layers 1 and 2 are computed
+// on the whole region as five 16-pixel strips; a value at the region's
+// outermost column is wrong (its neighbour outside the region is replaced by
+// the edge column) and the error moves inwards one column per layer, so
+// layer 2 is exact on columns 2..77 and the output layer, computed on the
+// four strips covering columns 8..71, is exact.  The standardised input rows
+// y0-3 .. y0+rows+2 are staged in LDS first, so the row loop issues no global
+// loads.  Layer rows stream through four-row rings: at step j the workgroup
+// computes layer-1 row y0+j-3, layer-2 row y0+j-5 and output row y0+j-7,
+// each from rows the previous three steps completed, with one barrier per
+// step.  Each wave has one role, which balances the matrix-core work (about
+// 36 MFMAs per wave and step) and keeps only that role's weights in
+// registers:
+//   wave 0: layer 2, strips 0 and 1      wave 2: layer 2, strip 4, and layer 1
+//   wave 1: layer 2, strips 2 and 3      wave 3: output layer, four strips
+// The arithmetic (tap order, FP32 accumulation, BF16 rounding points) is that
+// of k_prep and k_conv, so both paths give identical results.
+constexpr int kFuseCols = 80, kFuseOut = 64, kFuseWaves = 4, kRing = 4;
 constexpr int kFuseMaxRows = 32;
 // LDS pixel stride of the layer rings in BF16 elements: 32 channels padded to
 // 40 (80 bytes), which spreads the 16-byte reads of a fragment's 16 pixels
@@ -327,7 +332,8 @@ __global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
   __shared__ __attribute__((aligned(16))) bf16 in_tile[kFuseMaxRows + 6][kFuseCols][4];
   __shared__ __attribute__((aligned(16))) bf16 l1_ring[kRing][kFuseCols][kPixPad];
   __shared__ __attribute__((aligned(16))) bf16 l2_ring[kRing][kFuseCols][kPixPad];
-  const int tid = threadIdx.x, lane = tid & 63, s = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int n = lane & 15, g = lane >> 4;
   const int cb = blockIdx.x % a.ncb;
   const int rest = blockIdx.x / a.ncb;
@@ -335,109 +341,134 @@ __global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
   const int H = a.H, W = a.W, R = a.rows;
   const int x0 = cb * kFuseOut, y0 = rb * R;
 
-  // stage the standardised input: tile row q holds image row y0 - 3 + q
-  {
-    const int lc = tid % kFuseCols, lch = tid / kFuseCols;   // 320 threads = 80 x 4
+  // stage the standardised input: tile row q holds image row y0 - 3 + q.
+  // All rows' loads are issued before the first conversion, so the staging
+  // costs one memory latency rather than one per row.
+  for (int p = tid; p < kFuseCols * 4; p += 64 * kFuseWaves) {
+    const int lc = p % kFuseCols, lch = p / kFuseCols;
     int gx = x0 - 8 + lc;
     gx = gx < 0 ? gx + W : (gx >= W ? gx - W : gx);
     const float *src = a.x + b * a.sb + lch * a.sc + gx;
+    float v[kFuseMaxRows + 6];
+#pragma unroll
+    for (int q = 0; q < kFuseMaxRows + 6; ++q) {
+      if (q < R + 6) {
+        int yy = y0 - 3 + q;   // in [-3, H + 2]: one wrap suffices (H >= 4)
+        yy = yy < 0 ? yy + H : (yy >= H ? yy - H : yy);
+        v[q] = src[(long long)yy * W];
+      }
+    }
     const float mean = a.mean[lch], inv = a.inv_std[lch];
-    for (int q = 0; q < R + 6; ++q) {
-      int yy = (y0 - 3 + q) % H;
-      yy = yy < 0 ? yy + H : yy;
-      in_tile[q][lc][lch] = (bf16)((src[(long long)yy * W] - mean) * inv);
-    }
+#pragma unroll
+    for (int q = 0; q < kFuseMaxRows + 6; ++q)
+      if (q < R + 6) in_tile[q][lc][lch] = (bf16)((v[q] - mean) * inv);
   }
-
-  bf16x8 w1[2][2], w2[9][2], w3[9];
-#pragma unroll
-  for (int j = 0; j < 2; ++j)
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb) w1[j][nb] = a.wp[kPk1 + (j * 2 + nb) * 64 + lane];
-#pragma unroll
-  for (int t = 0; t < 9; ++t) {
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb) w2[t][nb] = a.wp[kPk2 + (t * 2 + nb) * 64 + lane];
-    w3[t] = a.wp[kPk3 + t * 64 + lane];
-  }
-  f32x4 bias1[2], bias2[2], bias3;
-#pragma unroll
-  for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      bias1[nb][r] = a.b1[16 * nb + 4 * g + r];
-      bias2[nb][r] = a.b2[16 * nb + 4 * g + r];
-    }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) bias3[r] = (4 * g + r < kOut) ? a.b3[4 * g + r] : 0.f;
-
-  const int col = s * 16 + n;                          // this lane's region column
-  // a neighbour outside the region reads the edge column instead: the value
-  // is wrong there either way and only the middle 64 columns are kept
+  // a neighbour outside the region reads the edge column instead
   auto clampc = [](int c) { return c < 0 ? 0 : (c >= kFuseCols ? kFuseCols - 1 : c); };
-  for (int j = 1; j <= R + 6; ++j) {
-    __syncthreads();
-    // layer rows completed at steps j-3, j-2, j-1 sit in ring slots
-    // (j+5+dy) & 3 for dy = 0, 1, 2; input row y0+j-4+dy is tile row j-1+dy
-    if (j <= R + 4) {                    // layer 1, row y0 + j - 3
-      f32x4 acc[2] = {bias1[0], bias1[1]};
-      bf16x4 v[2][2];
+  auto relu_store = [&](bf16 *dst, const f32x4 &acc) {
+    bf16x4 o;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[r] = (bf16)fmaxf(acc[r], 0.f);
+    *(bf16x4 *)dst = o;
+  };
+
+  if (wave < 3) {
+    // ---- layer 2 on strips s0 .. s0 + ns - 1 (and layer 1 for wave 2)
+    const int s0 = 2 * wave, ns = wave < 2 ? 2 : 1;
+    bf16x8 w2[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) w2[t][nb] = a.wp[kPk2 + (t * 2 + nb) * 64 + lane];
+    f32x4 bias2[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bias2[nb][r] = a.b2[16 * nb + 4 * g + r];
+    bf16x8 w1[2][2];
+    f32x4 bias1[2];
+    if (wave == 2) {
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int t = 8 * h + 2 * g + e;
-          const int tt = t < 9 ? t : 8;
-          const int dy = tt / 3, dx = tt - 3 * (tt / 3);
-          v[h][e] = *(const bf16x4 *)&in_tile[j - 1 + dy][clampc(col + dx - 1)][0];
-          if (t >= 9) v[h][e] = bf16x4{(bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f};
+        for (int nb = 0; nb < 2; ++nb) w1[h][nb] = a.wp[kPk1 + (h * 2 + nb) * 64 + lane];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bias1[nb][r] = a.b1[16 * nb + 4 * g + r];
+    }
+    for (int j = 1; j <= R + 6; ++j) {
+      __syncthreads();
+      if (wave == 2 && j <= R + 4) {     // layer 1, row y0 + j - 3: tile rows j-1+dy
+        for (int st = 0; st < 5; ++st) {
+          const int col = 16 * st + n;
+          bf16x4 v[2][2];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+              const int t = 8 * h + 2 * g + e;
+              const int tt = t < 9 ? t : 8;
+              const int dy = tt / 3, dx = tt - 3 * (tt / 3);
+              v[h][e] = *(const bf16x4 *)&in_tile[j - 1 + dy][clampc(col + dx - 1)][0];
+              if (t >= 9) v[h][e] = bf16x4{(bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f};
+            }
+          f32x4 acc[2] = {bias1[0], bias1[1]};
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const bf16x8 bv = __builtin_shufflevector(v[h][0], v[h][1], 0, 1, 2, 3, 4, 5, 6, 7);
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) acc[nb] = mfma(w1[h][nb], bv, acc[nb]);
+          }
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) relu_store(&l1_ring[j & 3][col][16 * nb + 4 * g], acc[nb]);
         }
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const bf16x8 bv = __builtin_shufflevector(v[h][0], v[h][1], 0, 1, 2, 3, 4, 5, 6, 7);
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) acc[nb] = mfma(w1[h][nb], bv, acc[nb]);
       }
+      if (j >= 4 && j <= R + 5) {        // layer 2, row y0 + j - 5
+        for (int st = s0; st < s0 + ns; ++st) {
+          const int col = 16 * st + n;
+          bf16x8 bv[9];
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        bf16x4 o;
+          for (int t = 0; t < 9; ++t)
+            bv[t] = *(const bf16x8 *)&l1_ring[(j + 5 + t / 3) & 3][clampc(col + t % 3 - 1)][8 * g];
+          f32x4 acc[2] = {bias2[0], bias2[1]};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) o[r] = (bf16)fmaxf(acc[nb][r], 0.f);
-        *(bf16x4 *)&l1_ring[j & 3][col][16 * nb + 4 * g] = o;
-      }
-    }
-    if (j >= 4 && j <= R + 5) {          // layer 2, row y0 + j - 5
-      f32x4 acc[2] = {bias2[0], bias2[1]};
-      bf16x8 bv[9];
+          for (int t = 0; t < 9; ++t)
 #pragma unroll
-      for (int t = 0; t < 9; ++t)
-        bv[t] = *(const bf16x8 *)&l1_ring[(j + 5 + t / 3) & 3][clampc(col + t % 3 - 1)][8 * g];
+            for (int nb = 0; nb < 2; ++nb) acc[nb] = mfma(w2[t][nb], bv[t], acc[nb]);
 #pragma unroll
-      for (int t = 0; t < 9; ++t)
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) acc[nb] = mfma(w2[t][nb], bv[t], acc[nb]);
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        bf16x4 o;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) o[r] = (bf16)fmaxf(acc[nb][r], 0.f);
-        *(bf16x4 *)&l2_ring[j & 3][col][16 * nb + 4 * g] = o;
+          for (int nb = 0; nb < 2; ++nb) relu_store(&l2_ring[j & 3][col][16 * nb + 4 * g], acc[nb]);
+        }
       }
     }
-    if (j >= 7) {                        // output, row y0 + j - 7
-      f32x4 acc = bias3;
-      bf16x8 bv[9];
+  } else {
+    // ---- output layer on the four strips covering columns 8 .. 71
+    bf16x8 w3[9];
 #pragma unroll
-      for (int t = 0; t < 9; ++t)
-        bv[t] = *(const bf16x8 *)&l2_ring[(j + 5 + t / 3) & 3][clampc(col + t % 3 - 1)][8 * g];
+    for (int t = 0; t < 9; ++t) w3[t] = a.wp[kPk3 + t * 64 + lane];
+    f32x4 bias3;
 #pragma unroll
-      for (int t = 0; t < 9; ++t) acc = mfma(w3[t], bv[t], acc);
-      if (g == 0 && col >= 8 && col < 8 + kFuseOut) {
-        const long long i = (long long)(y0 + j - 7) * W + x0 + col - 8;
+    for (int r = 0; r < 4; ++r) bias3[r] = (4 * g + r < kOut) ? a.b3[4 * g + r] : 0.f;
+    for (int j = 1; j <= R + 6; ++j) {
+      __syncthreads();
+      if (j < 7) continue;
+      const long long row = (long long)(y0 + j - 7) * W;
+      for (int st = 0; st < 4; ++st) {
+        const int col = 8 + 16 * st + n;
+        bf16x8 bv[9];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float ys = a.clip > 0.f ? fminf(fmaxf(acc[r], -a.clip), a.clip) : acc[r];
-          a.y[b * a.osb + r * a.osc + i] = ys * a.os[r] + a.om[r];
+        for (int t = 0; t < 9; ++t)
+          bv[t] = *(const bf16x8 *)&l2_ring[(j + 5 + t / 3) & 3][col + t % 3 - 1][8 * g];
+        f32x4 acc = bias3;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc = mfma(w3[t], bv[t], acc);
+        if (g == 0) {
+          const long long i = row + x0 + col - 8;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float ys = a.clip > 0.f ? fminf(fmaxf(acc[r], -a.clip), a.clip) : acc[r];
+            a.y[b * a.osb + r * a.osc + i] = ys * a.os[r] + a.om[r];
+          }
         }
       }
     }
