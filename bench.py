@@ -192,7 +192,7 @@ def learned_closure():
     setup = L.ClosureSetup()
     say = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     t0 = time.perf_counter()
-    net, rec = L.fit(setup, steps=10000, rollout_steps=0, clip=4.0, log=say)
+    net, rec = L.fit(setup, steps=20000, batch=32, lr=2e-3, clip=4.0, log=say)
     torch.cuda.synchronize()
     fit_s = time.perf_counter() - t0
     ev = L.evaluate(net, setup)
@@ -212,8 +212,9 @@ def learned_closure():
             "target_error_within_2x_plain512": bool(ev.e_learned <= 2 * ev.e_plain[512]),
             "target_10x_faster_than_fine": bool(ev.t_learned <= ev.t_plain[nf] / 10),
             "diverged": {str(k): v for k, v in ev.diverged.items()},
-            "train": {"pairs": rec["pairs"], "adam_steps": 10000, "batch": 16,
-                      "final_loss": round(rec["loss_phase1"][-1][1], 5), "fit_s": round(fit_s, 1)},
+            "train": {"pairs": rec["pairs"], "adam_steps": 20000, "batch": 32, "lr": 2e-3,
+                      "final_loss": round(rec["loss"][-1][1], 5), "fit_s": round(fit_s, 1),
+                      "correction_every": setup.every},
             "workload": f"decaying turbulence, Ma_t {setup.mach_range[0]}-{setup.mach_range[1]}, "
                         f"fine {nf}^2 (mu {setup.mu_fine}) restricted {setup.factor}x to {nc}^2; "
                         f"train seeds {len(setup.train_seeds)}, eval seeds "

@@ -125,13 +125,14 @@ int hlbm_restrict(const float *rho, const float *ux, const float *uy, const floa
 int hlbm_batch_correct(hlbm_batch *b, const float *x, const float *delta, int32_t conserve,
                        hlbm_stream_t stream);
 
-/* nsteps corrected steps of an HLBM_F32 batch: each is one batch step, the
- * moments, the network's increment and hlbm_batch_correct.  The network must
- * have been created for max_batch >= count and the domains' ny x nx; its
- * workspace holds the moments and increments.  use_graph = 1 replays a
- * captured two-step hipGraph (stream must not be NULL). */
-int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t nsteps, int32_t conserve,
-                      int32_t use_graph, hlbm_stream_t stream);
+/* ncycles correction cycles of an HLBM_F32 batch: each is `every` (>= 1)
+ * batch steps, then the moments, the network's increment and
+ * hlbm_batch_correct.  The network must have been created for max_batch >=
+ * count and the domains' ny x nx, and trained for increments over `every`
+ * steps; its workspace holds the moments and increments.  use_graph = 1
+ * replays a captured two-cycle hipGraph (stream must not be NULL). */
+int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t ncycles, int32_t every,
+                      int32_t conserve, int32_t use_graph, hlbm_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -105,7 +105,7 @@ def lib():
             "hlbm_restrict": (ctypes.c_int, [vp, vp, vp, vp, i32, i32, i32, i32, vp, i64, i64,
                                              vp]),
             "hlbm_batch_correct": (ctypes.c_int, [vp, vp, vp, i32, vp]),
-            "hlbm_closure_step": (ctypes.c_int, [vp, vp, i32, i32, i32, vp]),
+            "hlbm_closure_step": (ctypes.c_int, [vp, vp, i32, i32, i32, i32, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -420,10 +420,11 @@ class BatchSolver:
                                         _stream(self.stream)), "hlbm_batch_correct")
         self._leave()
 
-    def closure_step(self, net, n=1, conserve=True, graph=True):
-        """n steps, each followed by the network's correction."""
+    def closure_step(self, net, n=1, every=1, conserve=True, graph=True):
+        """n cycles of `every` steps, each cycle followed by the network's
+        correction."""
         self._enter()
-        _check(lib().hlbm_closure_step(self.h, net.h, int(n), int(bool(conserve)),
+        _check(lib().hlbm_closure_step(self.h, net.h, int(n), int(every), int(bool(conserve)),
                                        int(bool(graph)), _stream(self.stream)),
                "hlbm_closure_step")
         self._leave()

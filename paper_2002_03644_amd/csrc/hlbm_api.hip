@@ -359,7 +359,7 @@ struct hlbm_batch {
   hipGraphExec_t graph = nullptr;
   int graph_cur = -1;
   hipGraphExec_t cgraph = nullptr;    // captured corrected steps (hlbm_closure_step)
-  int cgraph_cur = -1, cgraph_conserve = -1, cgraph_version = -1;
+  int cgraph_cur = -1, cgraph_conserve = -1, cgraph_version = -1, cgraph_every = -1;
   const hlbm_cnn *cgraph_net = nullptr;
 };
 
@@ -733,10 +733,13 @@ hipError_t correct_launch(hlbm_batch *b, const float *x, const float *delta, int
                             conserve, st);
 }
 
-// one corrected step from buffer b->cur; advances b->cur
-int closure_once(hlbm_batch *b, hlbm_cnn *c, int conserve, hipStream_t st) {
-  if (batch_launch(b, b->cur, st) != hipSuccess) return HLBM_EHIP;
-  b->cur ^= 1;
+// `every` plain steps from buffer b->cur, then the network's correction;
+// advances b->cur
+int closure_once(hlbm_batch *b, hlbm_cnn *c, int every, int conserve, hipStream_t st) {
+  for (int k = 0; k < every; ++k) {
+    if (batch_launch(b, b->cur, st) != hipSuccess) return HLBM_EHIP;
+    b->cur ^= 1;
+  }
   float *x = hlbm_cnn_io(c, 0), *d = hlbm_cnn_io(c, 1);
   const long long n = (long long)b->params[0].nx * b->params[0].ny;
   const long long N = n * b->count;
@@ -757,19 +760,21 @@ int hlbm_batch_correct(hlbm_batch *b, const float *x, const float *delta, int32_
   return hip_status(correct_launch(b, x, delta, conserve ? 1 : 0, (hipStream_t)stream));
 }
 
-int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t nsteps, int32_t conserve,
-                      int32_t use_graph, hlbm_stream_t stream) {
-  if (!closure_ok(b) || !c || nsteps < 0) return HLBM_EINVAL;
+int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t ncycles, int32_t every,
+                      int32_t conserve, int32_t use_graph, hlbm_stream_t stream) {
+  if (!closure_ok(b) || !c || ncycles < 0 || every < 1) return HLBM_EINVAL;
   if (hlbm_cnn_max_batch(c) < b->count || hlbm_cnn_ny(c) != b->params[0].ny ||
       hlbm_cnn_nx(c) != b->params[0].nx)
     return HLBM_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   if (use_graph && !st) return HLBM_EINVAL;
   conserve = conserve ? 1 : 0;
-  int n = nsteps;
+  int n = ncycles;
   if (use_graph && n >= 2) {
+    // two cycles per graph: the state returns to the same buffer
     if (!b->cgraph || b->cgraph_cur != b->cur || b->cgraph_net != c ||
-        b->cgraph_conserve != conserve || b->cgraph_version != hlbm_cnn_version(c)) {
+        b->cgraph_conserve != conserve || b->cgraph_version != hlbm_cnn_version(c) ||
+        b->cgraph_every != every) {
       if (b->cgraph) {
         hipGraphExecDestroy(b->cgraph);
         b->cgraph = nullptr;
@@ -778,8 +783,8 @@ int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t nsteps, int32_t conser
       hipGraph_t g = nullptr;
       if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return HLBM_EHIP;
-      int rc1 = closure_once(b, c, conserve, st);
-      int rc2 = rc1 == HLBM_OK ? closure_once(b, c, conserve, st) : rc1;
+      int rc1 = closure_once(b, c, every, conserve, st);
+      int rc2 = rc1 == HLBM_OK ? closure_once(b, c, every, conserve, st) : rc1;
       hipError_t e = hipStreamEndCapture(st, &g);
       b->cur = cur0;   // capture only recorded the launches
       if (rc1 != HLBM_OK || rc2 != HLBM_OK || e != hipSuccess) {
@@ -796,16 +801,17 @@ int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t nsteps, int32_t conser
       b->cgraph_net = c;
       b->cgraph_conserve = conserve;
       b->cgraph_version = hlbm_cnn_version(c);
+      b->cgraph_every = every;
     }
     for (; n >= 2; n -= 2) {
       if (hipGraphLaunch(b->cgraph, st) != hipSuccess) return HLBM_EHIP;
-      b->steps += 2;
+      b->steps += 2 * every;
     }
   }
   for (; n > 0; --n) {
-    const int rc = closure_once(b, c, conserve, st);
+    const int rc = closure_once(b, c, every, conserve, st);
     if (rc != HLBM_OK) return rc;
-    b->steps++;
+    b->steps += every;
   }
   return HLBM_OK;
 }

@@ -413,6 +413,7 @@ __global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
               v[h][e] = *(const bf16x4 *)&in_tile[j - 1 + dy][clampc(col + dx - 1)][0];
               if (t >= 9) v[h][e] = bf16x4{(bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f};
             }
+          __builtin_amdgcn_sched_barrier(0);
           f32x4 acc[2] = {bias1[0], bias1[1]};
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
@@ -431,6 +432,8 @@ __global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
 #pragma unroll
           for (int t = 0; t < 9; ++t)
             bv[t] = *(const bf16x8 *)&l1_ring[(j + 5 + t / 3) & 3][clampc(col + t % 3 - 1)][8 * g];
+          // all nine reads in flight before the first MFMA waits on one
+          __builtin_amdgcn_sched_barrier(0);
           f32x4 acc[2] = {bias2[0], bias2[1]};
 #pragma unroll
           for (int t = 0; t < 9; ++t)
@@ -459,6 +462,7 @@ __global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
 #pragma unroll
         for (int t = 0; t < 9; ++t)
           bv[t] = *(const bf16x8 *)&l2_ring[(j + 5 + t / 3) & 3][col + t % 3 - 1][8 * g];
+        __builtin_amdgcn_sched_barrier(0);
         f32x4 acc = bias3;
 #pragma unroll
         for (int t = 0; t < 9; ++t) acc = mfma(w3[t], bv[t], acc);

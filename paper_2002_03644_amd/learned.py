@@ -11,11 +11,12 @@ Setup (the method's own data; the paper has no learned component):
   scaling (one coarse step = factor fine steps, mu_coarse = mu_fine /
   factor), initialised from the conservative block-mean restriction R of
   the fine state;
-* training pairs, per coarse step n: input Y_n = moments after one plain
-  coarse step from R(fine_{factor n}), target D_n = R(fine_{factor (n+1)}) - Y_n,
-  on (rho, u_x, u_y, theta), per-channel standardised;
-* inference: after every coarse step X <- X + CNN(X) with the mass and
-  momentum of each domain kept (hlbm_closure_step);
+* training pairs, per coarse step n: input Y_n = moments after `every`
+  plain coarse steps from R(fine_{factor n}), target
+  D_n = R(fine_{factor (n+every)}) - Y_n, on (rho, u_x, u_y, theta),
+  per-channel standardised;
+* inference: after every `every` coarse steps X <- X + CNN(X) with the mass
+  and momentum of each domain kept (hlbm_closure_step);
 * judge: the fine run restricted to the coarse grid; density error
   e = ||rho - rho_judge||_2 / ||rho_judge - <rho_judge>||_2 averaged over the
   held-out seeds and the checkpoints;
@@ -51,6 +52,7 @@ class ClosureSetup:
     checkpoints: tuple = (50, 100, 150, 200, 250)
     ladder: tuple = (384, 512, 768)
     chunk: int = 16            # fine domains per batched run
+    every: int = 10            # coarse steps per correction
 
     @property
     def coarse_n(self):
@@ -104,8 +106,8 @@ def restricted_trajectories(seeds, setup: ClosureSetup, steps=None, device="cuda
     return out, flags
 
 
-def coarse_one_step(X, thetas, setup: ClosureSetup, chunk=256):
-    """Moments after one plain coarse step from each state X[m] (float32
+def coarse_one_step(X, thetas, setup: ClosureSetup, chunk=256, steps=1):
+    """Moments after `steps` plain coarse steps from each state X[m] (float32
     [M][4][nc][nc]); thetas[m] is the storage reference of sample m."""
     import torch
     nc = setup.coarse_n
@@ -115,7 +117,7 @@ def coarse_one_step(X, thetas, setup: ClosureSetup, chunk=256):
         params = [_params(nc, setup.mu_coarse, float(thetas[c0 + j]), setup) for j in range(m)]
         fields = [(X[c0 + j, 0], X[c0 + j, 1], X[c0 + j, 2], X[c0 + j, 3]) for j in range(m)]
         B = BatchSolver(params, fields, device=X.device)
-        B.step(1, graph=False)
+        B.step(steps, graph=False)
         buf = torch.empty(4, m * nc * nc, dtype=torch.float32, device=X.device)
         B.moments_cat(out=buf, keys=("rho", "ux", "uy", "theta"))
         B.stream.synchronize()
@@ -125,61 +127,15 @@ def coarse_one_step(X, thetas, setup: ClosureSetup, chunk=256):
 
 
 def training_pairs(traj, seeds, setup: ClosureSetup):
-    """Inputs Y_n and targets D_n = X_{n+1} - Y_n of every seed and step,
-    flattened to [S][4][nc][nc] each."""
+    """Inputs Y_n and targets D_n = X_{n+every} - Y_n of every seed and
+    start n, flattened to [S][4][nc][nc] each."""
+    k = setup.every
     S, T1 = traj.shape[0], traj.shape[1]
-    X = traj[:, :-1].reshape(S * (T1 - 1), 4, setup.coarse_n, setup.coarse_n)
-    thetas = np.repeat([seed_flow(s, setup)[1] for s in seeds], T1 - 1)
-    Y = coarse_one_step(X, thetas, setup)
-    D = traj[:, 1:].reshape_as(Y) - Y
+    X = traj[:, :-k].reshape(S * (T1 - k), 4, setup.coarse_n, setup.coarse_n)
+    thetas = np.repeat([seed_flow(s, setup)[1] for s in seeds], T1 - k)
+    Y = coarse_one_step(X, thetas, setup, steps=k)
+    D = traj[:, k:].reshape_as(Y) - Y
     return Y, D
-
-
-def rollout_pairs(net: CNN, traj, seeds, setup: ClosureSetup, starts=None, horizon=20,
-                  chunk=64, clip=None, max_rms=5.0):
-    """Pairs along the network's own corrected trajectories: from R(fine_n0)
-    for every start n0, `horizon` coarse steps, each a plain step whose
-    moments Y_n are the input, with target D_n = R(fine_{factor (n+1)}) - Y_n,
-    followed by the network's increment.  Samples with a non-finite value or
-    a target RMS above max_rms times the one-step targets' are dropped.
-    Returns float32 [S][4][nc][nc] inputs and targets."""
-    import torch
-    nc, n = setup.coarse_n, setup.coarse_n ** 2
-    S, T1 = traj.shape[0], traj.shape[1]
-    starts = list(range(0, T1 - 1, 25)) if starts is None else list(starts)
-    ref = (traj[:, 1:2] - traj[:, 0:1]).float().pow(2).mean().sqrt()
-    Ys, Ds = [], []
-    for c0 in range(0, S, chunk):
-        m = min(chunk, S - c0)
-        sds = list(seeds[c0:c0 + m])
-        params = [_params(nc, setup.mu_coarse, seed_flow(s, setup)[1], setup) for s in sds]
-        inf = CNN(m, nc, nc, net.params(), device=traj.device)
-        inf.set_norm(*np.split(net.norm, 4))
-        if clip:
-            inf.set_output_clip(clip)
-        x = torch.empty(4, m * n, dtype=torch.float32, device=traj.device)
-        for n0 in starts:
-            h = min(horizon, T1 - 1 - n0)
-            x0 = traj[c0:c0 + m, n0]
-            B = BatchSolver(params, [(x0[j, 0], x0[j, 1], x0[j, 2], x0[j, 3]) for j in range(m)],
-                            device=traj.device)
-            Y = torch.empty(m, h, 4, nc, nc, dtype=torch.float32, device=traj.device)
-            for k in range(h):
-                B.step(1, graph=False)
-                B.moments_cat(out=x, keys=("rho", "ux", "uy", "theta"))
-                B.stream.synchronize()
-                Y[:, k] = x.view(4, m, nc, nc).permute(1, 0, 2, 3)
-                d = inf.forward(x, batch=m, sstride=n, cstride=m * n)
-                B.correct(x, d.permute(1, 0, 2, 3).reshape(4, m * n).contiguous(), conserve=True)
-            D = traj[c0:c0 + m, n0 + 1:n0 + 1 + h] - Y
-            ok = torch.isfinite(Y).flatten(2).all(dim=2) & torch.isfinite(D).flatten(2).all(dim=2)
-            rms = torch.nan_to_num(D, nan=1e30).pow(2).flatten(3).mean(dim=3).mean(dim=2).sqrt()
-            ok &= rms <= max_rms * ref * 2.0
-            Ys.append(Y[ok])
-            Ds.append(D[ok])
-            del B
-        del inf
-    return torch.cat(Ys), torch.cat(Ds)
 
 
 def channel_stats(A):
@@ -190,13 +146,9 @@ def channel_stats(A):
     return mean.float().cpu().numpy(), std.float().cpu().numpy()
 
 
-def train(net: CNN, Y, D, steps, batch=16, lr=1e-3, seed=0, log_every=500, lr_final=None,
-          noise=0.0):
+def train(net: CNN, Y, D, steps, batch=32, lr=2e-3, seed=0, log_every=500, lr_final=None):
     """Adam on random minibatches of the pairs (Y, D); cosine learning-rate
-    decay to lr_final.  With noise > 0 each minibatch input gets Gaussian
-    noise of `noise` times the channel's standard deviation and its target
-    the opposite of it, so the network also learns to remove such errors.
-    Returns the logged (step, loss) pairs."""
+    decay from lr to lr_final.  Returns the logged (step, loss) pairs."""
     import torch
     g = torch.Generator(device=Y.device)
     g.manual_seed(seed)
@@ -204,18 +156,10 @@ def train(net: CNN, Y, D, steps, batch=16, lr=1e-3, seed=0, log_every=500, lr_fi
     lr_final = lr * 0.05 if lr_final is None else lr_final
     log = []
     loss = torch.zeros(1, dtype=torch.float32, device=Y.device)
-    if noise > 0:
-        sig = torch.from_numpy(net.norm[4:8] * noise).to(Y.device).view(1, 4, 1, 1)
     for k in range(steps):
         idx = torch.randint(0, S, (batch,), generator=g, device=Y.device, dtype=torch.int32)
         lr_k = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * k / max(1, steps)))
-        if noise > 0:
-            eps = torch.randn((batch,) + tuple(Y.shape[1:]), generator=g, device=Y.device) * sig
-            li = idx.long()
-            net.train_step((Y[li] + eps).contiguous(), (D[li] - eps).contiguous(), lr_k,
-                           loss=loss)
-        else:
-            net.train_step(Y, D, lr_k, idx=idx, loss=loss)
+        net.train_step(Y, D, lr_k, idx=idx, loss=loss)
         if log_every and (k % log_every == 0 or k == steps - 1):
             log.append((k, float(loss.item())))
     return log
@@ -338,43 +282,26 @@ def build_network(Y, D, setup: ClosureSetup, max_batch=16, seed=0):
     return net
 
 
-def fit(setup: ClosureSetup, steps=10000, rollout_steps=10000, batch=16, lr=1e-3, clip=4.0,
-        seed=0, noise=0.0, horizon=20, log=print):
+def fit(setup: ClosureSetup, steps=20000, batch=32, lr=2e-3, clip=4.0, seed=0, log=print):
     """Train the closure network for `setup`: restricted fine trajectories of
-    the training seeds, one-step pairs, `steps` Adam steps; then pairs along
-    the network's own corrected trajectories added to the set and
-    `rollout_steps` more Adam steps.  Returns the network (clamp `clip` set)
-    and a record of the run."""
+    the training seeds, the (input, target) pairs, `steps` Adam steps.
+    Returns the network (output clamp `clip` set) and a record of the run."""
     import torch
     t0 = time.perf_counter()
     traj, flags = restricted_trajectories(setup.train_seeds, setup)
     Y, D = training_pairs(traj, setup.train_seeds, setup)
+    del traj
     rec = {"fine_diverged": int(flags.sum()), "pairs": int(Y.shape[0]),
            "data_s": time.perf_counter() - t0}
-    log(f"[closure] {Y.shape[0]} one-step pairs in {rec['data_s']:.1f} s")
+    log(f"[closure] {Y.shape[0]} pairs ({setup.every}-step targets) in {rec['data_s']:.1f} s")
     net = build_network(Y, D, setup, max_batch=batch, seed=seed)
     t0 = time.perf_counter()
-    rec["loss_phase1"] = train(net, Y, D, steps, batch=batch, lr=lr, seed=seed, noise=noise)
+    rec["loss"] = train(net, Y, D, steps, batch=batch, lr=lr, seed=seed)
     torch.cuda.synchronize()
-    rec["train1_s"] = time.perf_counter() - t0
-    log(f"[closure] phase 1: {steps} steps in {rec['train1_s']:.1f} s, "
-        f"loss {rec['loss_phase1'][-1][1]:.4f}")
-    if rollout_steps:
-        t0 = time.perf_counter()
-        Yr, Dr = rollout_pairs(net, traj, setup.train_seeds, setup, clip=clip, horizon=horizon)
-        rec["rollout_pairs"] = int(Yr.shape[0])
-        Y = torch.cat([Y, Yr])
-        D = torch.cat([D, Dr])
-        del Yr, Dr
-        rec["rollout_s"] = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        rec["loss_phase2"] = train(net, Y, D, rollout_steps, batch=batch, lr=lr * 0.5,
-                                   seed=seed + 1, noise=noise)
-        torch.cuda.synchronize()
-        rec["train2_s"] = time.perf_counter() - t0
-        log(f"[closure] phase 2: +{rec['rollout_pairs']} rollout pairs, {rollout_steps} steps "
-            f"in {rec['train2_s']:.1f} s, loss {rec['loss_phase2'][-1][1]:.4f}")
-    del traj, Y, D
+    rec["train_s"] = time.perf_counter() - t0
+    log(f"[closure] {steps} Adam steps (batch {batch}) in {rec['train_s']:.1f} s, "
+        f"loss {rec['loss'][-1][1]:.4f}")
+    del Y, D
     if clip:
         net.set_output_clip(clip)
     return net, rec
@@ -432,7 +359,11 @@ def evaluate(net: CNN, setup: ClosureSetup, seeds=None, ladder=None, judge=None,
         inf.set_norm(*np.split(net.norm, 4))
         inf.set_output_clip(getattr(net, "clip", 0.0))
         net = inf
-    learned = lambda B, n: B.closure_step(net, n, conserve=True, graph=True)  # noqa: E731
+    k = setup.every
+    if any(c % k for c in cps) or steps % k:
+        raise ValueError("checkpoints must be whole correction cycles")
+    learned = lambda B, n: B.closure_step(net, n // k, every=k, conserve=True,  # noqa: E731
+                                          graph=True)
     plain = lambda B, n: B.step(n, graph=True)  # noqa: E731
     ns = len(seeds)
     diverged = {}

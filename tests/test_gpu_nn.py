@@ -230,7 +230,11 @@ def test_correction_moves_only_the_equilibrium():
     np.testing.assert_allclose(s1[9] - s0[9], ds, rtol=0, atol=2e-6)
 
 
-def test_closure_step_graph_equals_eager_and_manual_sequence():
+@pytest.mark.parametrize("every", [1, 2, 3])
+def test_closure_step_graph_equals_eager_and_manual_sequence(every):
+    """Corrected cycles (`every` plain steps, then the correction): graph
+    replay, eager launches and a manual step / moments / forward / correct
+    sequence agree bit for bit."""
     params, flds = closure_batch(count=3, n=64, seed=30)
     net_params = rand_params(31)
     net_params[2] = (net_params[2][0] * 0.01, net_params[2][1] * 0.0)
@@ -243,10 +247,10 @@ def test_closure_step_graph_equals_eager_and_manual_sequence():
                     np.zeros(4, np.float32), np.array([1e-4, 1e-4, 1e-4, 1e-5], np.float32))
     x = torch.empty(4, 3, 64 * 64, device="cuda")
     for rep in range(3):
-        A.closure_step(na, 4, graph=True)
-        E.closure_step(ne, 4, graph=False)
+        A.closure_step(na, 4, every=every, graph=True)
+        E.closure_step(ne, 4, every=every, graph=False)
         for _ in range(4):
-            M.step(1, graph=False)
+            M.step(every, graph=False)
             x.copy_(moments_cat(M))
             dl = nm.forward(x, batch=3, sstride=64 * 64, cstride=3 * 64 * 64)
             d = dl.permute(1, 0, 2, 3).reshape(4, 3, -1).contiguous()
@@ -256,7 +260,7 @@ def test_closure_step_graph_equals_eager_and_manual_sequence():
         assert torch.equal(ma, me), rep
         assert torch.equal(ma, mm), rep
         assert torch.isfinite(ma).all()
-    assert A.steps == E.steps == 12
+    assert A.steps == E.steps == M.steps == 12 * every
 
 
 @pytest.mark.parametrize("B,H,W", [(3, 12, 64), (2, 256, 256), (1, 36, 128), (5, 8, 192)])
