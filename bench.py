@@ -87,16 +87,20 @@ def main():
     ap.add_argument("--tile-w", type=int, default=0)
     ap.add_argument("--tile-h", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--map-dtype", default="f64", choices=["f32", "f64"],
+                    help="precision of the vortex-map workload")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-closure part (training + evaluation, about a minute)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 2 GiB device copy (counter calibration)")
     ap.add_argument("--workload", default="turbulence8192",
-                    choices=["turbulence8192", "batch256", "closure"],
+                    choices=["turbulence8192", "batch256", "closure", "vortex-map"],
                     help="batch256: the 256-domain batch (one persistent launch per step, "
                          "graph-replayed), reported as aggregate MLUPS of the domains still "
                          "active at the end; closure: the corrected coarse step of the "
-                         "learned closure (8 x 256^2) and the network's training step")
+                         "learned closure (8 x 256^2) and the network's training step; "
+                         "vortex-map: the sigma x Mach isentropic-vortex study of Sec. 4.2 "
+                         "(200^2, 50 convective times, 11 x 11 runs plus the original model)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -106,6 +110,8 @@ def main():
         return bench_batch(args)
     if args.workload == "closure":
         return bench_closure(args)
+    if args.workload == "vortex-map":
+        return bench_vortex_map(args)
 
     import numpy as np
     import torch
@@ -282,6 +288,27 @@ def bench_closure(args):
            "train_step_us_batch16": round(ms_t / nt * 1e3, 1),
            "network_flop_per_field": fwd_flop,
            "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
+def bench_vortex_map(args):
+    """The sigma x Mach map of the convected isentropic vortex (FP64 by
+    default), one batch (11 sigma values + the original model) per Mach
+    number."""
+    from paper_2002_03644_amd import studies
+    say = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    res = studies.sigma_mach_map(log=say, dtype=args.map_dtype)
+    summ = studies.map_summary(res)
+    out = {"metric": "sigma x Mach vortex map: aggregate lattice updates per second",
+           "value": round(res.node_updates / res.seconds / 1e6, 1), "unit": "MLUPS",
+           "n_gpus": 1, "steps": int(sum(res.steps.values())), "warmup": 0,
+           "ms_per_step": round(res.seconds * 1e3 / sum(res.steps.values()), 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": args.map_dtype, "data": "synthetic",
+           "config": {"workload": "isentropic vortex 200^2 periodic, R 20, Ma_v = 0.1 Ma, "
+                                  "theta 240/1183, mu 1.5e-6, 50 convective times, "
+                                  "Ma 0.3..1.3 x sigma 0..1 (+ original model at sigma 0)"},
+           "map": summ, "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
 

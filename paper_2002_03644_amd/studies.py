@@ -1,0 +1,127 @@
+"""Parameter studies of the method, run on the batched engine.
+
+sigma_mach_map: the convected isentropic vortex of Sec. 4.2 on a periodic
+n x n box (R = n / 10 points per radius, vortex intensity Ma_v = 0.1 Ma),
+one temperature for every Mach number (theta = 240/1183, the paper's
+T/T_r = 300 / 1478.75), advected along x for 50 convective times L / u_inf
+-- after which the exact solution is the initial field again -- for a grid
+of HRR blends sigma and Mach numbers, and, at sigma = 0, the original model
+(centred E1, no E2).  Per run: the L2 error of the pressure relative to the
+vortex's pressure perturbation, ||p - p_0||_2 / ||p_0 - p_inf||_2, a
+divergence flag (non-finite or non-physical state), and an energy flag set
+when the largest total-energy density p / (gamma - 1) + rho |u|^2 / 2 grew
+above the initial one by more than 1e-4 of it (the paper marks runs that
+diverged or whose total-energy maximum grew as failed).  All sigma values of one Mach number (and the
+original model) advance together as one batch.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+import hlbm_inputs as hi
+
+from ._lib import BatchSolver, Params
+
+
+@dataclass
+class MapResult:
+    machs: list
+    sigmas: list
+    n: int
+    conv_times: float
+    steps: dict = field(default_factory=dict)        # mach -> steps run
+    error: dict = field(default_factory=dict)        # (model, mach, sigma) -> e_p (None if diverged)
+    diverged: dict = field(default_factory=dict)     # (model, mach, sigma) -> bool
+    energy_grew: dict = field(default_factory=dict)  # (model, mach, sigma) -> bool
+    seconds: float = 0.0
+    node_updates: float = 0.0
+
+    def failed(self, model, mach, sigma):
+        return self.diverged[(model, mach, sigma)] or self.energy_grew[(model, mach, sigma)]
+
+
+def _pressure(rho, theta):
+    return rho * hi.CS2 * theta
+
+
+def sigma_mach_map(machs=None, sigmas=None, n=200, conv_times=50.0, beta=0.1, mu=1.5e-6,
+                   gamma=1.4, theta=hi.THETA_PAPER, dtype="f32", original=True,
+                   device="cuda", log=None):
+    """Run the map (see the module docstring).  mu defaults to the paper's
+    air viscosity (1e-5 kg/(m s) at 300 K, 1 atm) in the lattice units of its
+    200-point, 1 m box with T_r = 1478.75 K."""
+    import torch
+    machs = [round(0.3 + 0.1 * k, 10) for k in range(11)] if machs is None else list(machs)
+    sigmas = [round(0.1 * k, 10) for k in range(11)] if sigmas is None else list(sigmas)
+    R = n / 10.0
+    c = hi.sound_speed(gamma, theta)
+    res = MapResult(machs, sigmas, n, conv_times)
+    t0 = time.perf_counter()
+    for mach in machs:
+        steps = int(round(conv_times * n / (mach * c)))
+        mach_eff = conv_times * n / (steps * c)      # whole number of box crossings
+        f = hi.vortex(n, n, n / 2, n / 2, R, mach_eff, beta * mach_eff, gamma=gamma,
+                      theta_inf=theta, periodic_images=True)
+        models = [("present", s) for s in sigmas] + ([("original", 0.0)] if original else [])
+        params = [Params(n, n, dtype=dtype, gamma=gamma, mu=mu, sigma=s, theta_ref=theta,
+                         e1_centred=(m == "original"), e2_off=(m == "original"))
+                  for m, s in models]
+        B = BatchSolver(params, [f] * len(models), device=device)
+        B.autotune(steps=3)
+        B.step(steps, graph=True)
+        _, flags = B.status()
+        mom = B.moments()
+        p0 = _pressure(f[0], f[3])
+        p_inf = _pressure(1.0, theta)
+        e0 = p0 / (gamma - 1.0) + 0.5 * f[0] * (f[1] ** 2 + f[2] ** 2)
+        den = np.linalg.norm(p0 - p_inf)
+        for k, (m, s) in enumerate(models):
+            d = {key: v.double().cpu().numpy() for key, v in mom[k].items()}
+            p = _pressure(d["rho"], d["theta"])
+            ok = bool(flags[k] == 0 and np.isfinite(p).all())
+            res.error[(m, mach, s)] = float(np.linalg.norm(p - p0) / den) if ok else None
+            res.diverged[(m, mach, s)] = not ok
+            grew = False
+            if ok:
+                et = p / (gamma - 1.0) + 0.5 * d["rho"] * (d["ux"] ** 2 + d["uy"] ** 2)
+                grew = bool(et.max() > e0.max() * (1.0 + 1e-4))
+            res.energy_grew[(m, mach, s)] = grew
+        res.steps[mach] = steps
+        res.node_updates += float(steps) * n * n * len(models)
+        if log:
+            def cell(m, s):
+                if res.diverged[(m, mach, s)]:
+                    return "x"
+                return f"{res.error[(m, mach, s)]:.3g}" + ("*" if res.energy_grew[(m, mach, s)] else "")
+            log(f"[map] Ma {mach:.1f}: {steps} steps, e_p(sigma) = "
+                + " ".join(cell("present", s) for s in sigmas)
+                + (f", original {cell('original', 0.0)}" if original else ""))
+        del B
+    torch.cuda.synchronize()
+    res.seconds = time.perf_counter() - t0
+    return res
+
+
+def map_summary(res: MapResult):
+    """JSON-friendly form of a map."""
+    def key(m, s):
+        return f"{m:.1f}/{s:.1f}"
+    out = {"machs": res.machs, "sigmas": res.sigmas, "n": res.n, "conv_times": res.conv_times,
+           "steps": {f"{m:.1f}": v for m, v in res.steps.items()},
+           "present": {key(m, s): res.error[("present", m, s)] for m in res.machs
+                       for s in res.sigmas},
+           "present_diverged": [key(m, s) for m in res.machs for s in res.sigmas
+                                if res.diverged[("present", m, s)]],
+           "present_energy_grew": [key(m, s) for m in res.machs for s in res.sigmas
+                                   if res.energy_grew[("present", m, s)]],
+           "seconds": round(res.seconds, 2),
+           "glups": round(res.node_updates / max(res.seconds, 1e-9) / 1e9, 2)}
+    if ("original", res.machs[0], 0.0) in res.error:
+        out["original_sigma0"] = {f"{m:.1f}": res.error[("original", m, 0.0)] for m in res.machs}
+        out["original_diverged"] = [f"{m:.1f}" for m in res.machs
+                                    if res.diverged[("original", m, 0.0)]]
+    return out
+
