@@ -125,3 +125,37 @@ def map_summary(res: MapResult):
                                     if res.diverged[("original", m, 0.0)]]
     return out
 
+
+
+def acoustic_pulse(n=201, R=6.0, amp_pa=10.0, p_inf_pa=101323.0, t_frac=0.4, gamma=1.4,
+                   theta=hi.THETA_PAPER, mu=1.5e-6, dtype="f64", device="cuda"):
+    """The Gaussian acoustic pulse of Sec. 5.1 at Ma = 0 (sigma 0.95, centred)
+    and Ma = 1 (sigma 0, started at x = n / 10 so both end at the centre),
+    one batch of the two on a periodic n x n box: p = p_inf (1 + A
+    exp(-r^2 / (2 R^2))) with A = amp_pa / p_inf_pa, isentropic rho and
+    theta, u_x = Ma c.  Runs round(t_frac n / c) steps.  Returns, per Mach
+    number, the pressure perturbation p - p_inf [n][n] (FP64 numpy), its
+    initial centre (x0, y0) in cells, the mean velocity, and the steps."""
+    c = hi.sound_speed(gamma, theta)
+    steps = int(round(t_frac * n / c))
+    p_inf = hi.CS2 * theta
+    X, Y = np.meshgrid(np.arange(n, dtype=np.float64), np.arange(n, dtype=np.float64))
+    cases = [(0.0, 0.95, n // 2), (1.0, 0.0, n // 10)]
+    params, fields = [], []
+    for mach, sigma, xc in cases:
+        dx = (X - xc + n / 2) % n - n / 2
+        dy = (Y - n // 2 + n / 2) % n - n / 2
+        p = p_inf * (1.0 + amp_pa / p_inf_pa * np.exp(-(dx * dx + dy * dy) / (2.0 * R * R)))
+        rho = (p / p_inf) ** (1.0 / gamma)
+        fields.append((rho, np.full((n, n), mach * c), np.zeros((n, n)), p / (rho * hi.CS2)))
+        params.append(Params(n, n, dtype=dtype, gamma=gamma, mu=mu, sigma=sigma, theta_ref=theta))
+    B = BatchSolver(params, fields, device=device)
+    B.step(steps, graph=True)
+    mom = B.moments()
+    out = {}
+    for k, (mach, sigma, xc) in enumerate(cases):
+        d = {key: v.double().cpu().numpy() for key, v in mom[k].items()}
+        out[mach] = {"p_prime": _pressure(d["rho"], d["theta"]) - p_inf, "x0": float(xc),
+                     "y0": float(n // 2), "u": mach * c, "steps": steps, "sigma": sigma,
+                     "amp": p_inf * amp_pa / p_inf_pa, "c": c, "R": R}
+    return out

@@ -316,3 +316,20 @@ def test_original_model_diverges_present_model_stable(mach):
 
     assert survives()
     assert not survives(e1_centred=True, e2_off=True, feq_order=3)
+
+
+def test_acoustic_pulse_reference_closed_form_checks():
+    """The 2-D pulse reference: at t = 0 it is the Gaussian itself; for
+    large t the front travels at c (peak of r^(1/2) p' near r = c t); its
+    space integral (the monopole) stays eps pi / alpha."""
+    from acoustics_exact import pulse_pressure
+    alpha, c = 1.0 / (2 * 6.0 ** 2), 0.3
+    r = np.linspace(0, 60, 301)
+    np.testing.assert_allclose(pulse_pressure(r, 0.0, c, alpha), np.exp(-alpha * r * r), atol=1e-6)
+    t = 150.0
+    p = pulse_pressure(r, t, c, alpha)
+    rp = r[np.argmax(np.sqrt(r) * np.abs(p))]
+    assert abs(rp - c * t) < 6.0
+    rr = np.linspace(0, 200, 4001)
+    integral = np.trapezoid(2 * np.pi * rr * pulse_pressure(rr, 60.0, c, alpha), rr)
+    assert integral == pytest.approx(np.pi / alpha, rel=1e-3)
