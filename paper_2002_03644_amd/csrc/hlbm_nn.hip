@@ -41,7 +41,7 @@ struct hlbm_cnn {
   float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
   bf16 *packed = nullptr;
   bf16 *xn = nullptr, *a1 = nullptr, *a2 = nullptr, *g3 = nullptr, *g2 = nullptr, *g1 = nullptr;
-  float *y = nullptr, *io_x = nullptr, *io_d = nullptr, *wpart = nullptr;
+  float *y = nullptr, *io_x = nullptr, *io_d = nullptr, *wpart = nullptr, *wcol = nullptr;
   double *lpart = nullptr;
   size_t total = 0;
   float norm[16];
@@ -76,6 +76,7 @@ void layout(hlbm_cnn *c, char *base) {
   c->g2 = (bf16 *)take(sizeof(bf16) * kHid * px);
   c->g1 = (bf16 *)take(sizeof(bf16) * kHid * px);
   c->wpart = (float *)take(sizeof(float) * kPartFloats * (size_t)parts);
+  c->wcol = (float *)take(sizeof(float) * kPartFloats * (size_t)kWgGroups);
   c->lpart = (double *)take(sizeof(double) * kLossParts + sizeof(float));
   c->io_x = (float *)take(sizeof(float) * 4 * px);
   c->io_d = (float *)take(sizeof(float) * 4 * px);
@@ -160,8 +161,10 @@ hipError_t wgrad(hlbm_cnn *c, int B, const bf16 *in, const bf16 *g, int off, hip
   const int parts = B * a.nsx * a.nry;
   hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(parts), dim3(192), 0, st, a);
   constexpr int P = 9 * CIN * COUT + COUT;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3((P + 255) / 256), dim3(256), 0, st,
-                     (const float *)c->wpart, parts, P, c->grads + off);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((P + 255) / 256, kWgGroups), dim3(256), 0, st,
+                     (const float *)c->wpart, parts, P, c->wcol);
+  hipLaunchKernelGGL(k_wgrad_final, dim3((P + 255) / 256), dim3(256), 0, st,
+                     (const float *)c->wcol, P, c->grads + off);
   return hipGetLastError();
 }
 

@@ -623,13 +623,35 @@ __global__ __launch_bounds__(192) void k_wgrad(WgradArgs a) {
   }
 }
 
-// Sum of the per-workgroup partials (fixed order) into the canonical
-// gradient of one layer.
-__global__ void k_wgrad_reduce(const float *partials, int nparts, int P, float *grad) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// Sum of the per-workgroup partials into the canonical gradient of one
+// layer, in two fixed-order passes: workgroup column g sums partials g,
+// g + G, g + 2G, ... for 256 parameters, then k_wgrad_final adds the G
+// column sums.
+constexpr int kWgGroups = 32;
+
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float *partials, int nparts, int P,
+                                                       float *colsum) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int g = blockIdx.y;
+  if (j >= P) return;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  int u = g;
+  for (; u + 3 * kWgGroups < nparts; u += 4 * kWgGroups) {
+    s0 += partials[(size_t)u * P + j];
+    s1 += partials[(size_t)(u + kWgGroups) * P + j];
+    s2 += partials[(size_t)(u + 2 * kWgGroups) * P + j];
+    s3 += partials[(size_t)(u + 3 * kWgGroups) * P + j];
+  }
+  for (; u < nparts; u += kWgGroups) s0 += partials[(size_t)u * P + j];
+  colsum[(size_t)g * P + j] = (s0 + s1) + (s2 + s3);
+}
+
+__global__ __launch_bounds__(256) void k_wgrad_final(const float *colsum, int P, float *grad) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= P) return;
   float s = 0.f;
-  for (int u = 0; u < nparts; ++u) s += partials[(size_t)u * P + j];
+#pragma unroll 8
+  for (int g = 0; g < kWgGroups; ++g) s += colsum[(size_t)g * P + j];
   grad[j] = s;
 }
 
