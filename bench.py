@@ -276,7 +276,14 @@ def bench_closure(args):
     trn.train_step(Y, D, 1e-3, idx=idx)
     ms_t = timed(lambda: [trn.train_step(Y, D, 1e-3, idx=idx) for _ in range(nt)],
                  torch.cuda.current_stream())
-    fwd_flop = 2.0 * 65536 * 9 * (4 * 32 + 32 * 32 + 32 * 4)
+    fwd_flop = 2.0 * nc * nc * 9 * (4 * 32 + 32 * 32 + 32 * 4)
+    # the fused inference kernel alone: one launch per forward call
+    x = torch.randn(len(seeds), 4, nc, nc, device="cuda") * 0.01
+    y = torch.empty_like(x)
+    nf = max(20, args.steps)
+    net.forward(x, out=y)
+    ms_f = timed(lambda: [net.forward(x, out=y) for _ in range(nf)], torch.cuda.current_stream())
+    tflops = fwd_flop * len(seeds) / (ms_f / nf / 1e3) / 1e12
     out = {"metric": "corrected coarse step time (8 x 256^2)",
            "value": round(ms_c / args.steps * 1e3, 2), "unit": "us/step", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup,
@@ -287,7 +294,11 @@ def bench_closure(args):
            "plain_step_us": round(ms_p / args.steps * 1e3, 2),
            "train_step_us_batch16": round(ms_t / nt * 1e3, 1),
            "network_flop_per_field": fwd_flop,
-           "roofline": None, "cpu_baseline": None}
+           "cnn_forward_us": round(ms_f / nf * 1e3, 2),
+           "roofline": {"bound": "mfma", "kernel": "k_cnn_fused", "achieved": round(tflops, 1),
+                        "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tflops / 2500.0, 4),
+                        "traffic": None},
+           "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
 
