@@ -110,3 +110,36 @@ def test_cnn_workspace_validates_dims(dims, ok):
     if ok:   # at least the activations: 4 + 32 + 32 (+ gradients) BF16 channels per pixel
         b, h, w = dims
         assert n >= b * h * w * 2 * (4 + 32 + 32 + 4 + 32 + 32)
+
+
+def test_nn_entry_points_validate_on_the_host():
+    """Invalid arguments are rejected before any device work (no GPU needed)."""
+    import ctypes
+
+    from paper_2002_03644_amd import _lib
+    L = _lib.lib()
+    EINVAL, EWS = _lib.HLBM_EINVAL, _lib.HLBM_EWORKSPACE
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    # bad sizes, missing parameters, missing or short workspace
+    assert L.hlbm_cnn_init(ctypes.byref(h), 0, 256, 256, fake, 1 << 30, fake, None) == EINVAL
+    assert L.hlbm_cnn_init(ctypes.byref(h), 1, 256, 250, fake, 1 << 30, fake, None) == EINVAL
+    assert L.hlbm_cnn_init(ctypes.byref(h), 1, 256, 256, fake, 1 << 30, None, None) == EINVAL
+    assert L.hlbm_cnn_init(ctypes.byref(h), 1, 32, 64, None, 0, fake, None) == EWS
+    need = L.hlbm_cnn_workspace_bytes(1, 32, 64)
+    assert L.hlbm_cnn_init(ctypes.byref(h), 1, 32, 64, fake, need - 1, fake, None) == EWS
+    assert h.value is None
+    # null handles
+    assert L.hlbm_cnn_set_norm(None, (ctypes.c_float * 16)()) == EINVAL
+    assert L.hlbm_cnn_set_output_clip(None, 1.0) == EINVAL
+    assert L.hlbm_cnn_set_fused(None, 1) == EINVAL
+    assert L.hlbm_cnn_adam(None, 1e-3, None) == EINVAL
+    assert L.hlbm_cnn_forward(None, fake, 4, 1, None, 1, fake, 4, 1, None) == EINVAL
+    assert L.hlbm_cnn_loss_grad(None, fake, 4, 1, fake, 4, 1, None, 1, None, None) == EINVAL
+    assert L.hlbm_batch_correct(None, fake, fake, 1, None) == EINVAL
+    assert L.hlbm_closure_step(None, None, 1, 1, 1, 1, None) == EINVAL
+    # restriction: sizes must divide, pointers and strides must be given
+    assert L.hlbm_restrict(fake, fake, fake, fake, 1, 10, 12, 4, fake, 16, 4, None) == EINVAL
+    assert L.hlbm_restrict(fake, fake, fake, None, 1, 16, 16, 4, fake, 64, 16, None) == EINVAL
+    assert L.hlbm_restrict(fake, fake, fake, fake, 1, 16, 16, 4, fake, 0, 16, None) == EINVAL
+    assert L.hlbm_restrict(fake, fake, fake, fake, 0, 16, 16, 4, fake, 64, 16, None) == EINVAL
