@@ -39,7 +39,8 @@ class _Params(ctypes.Structure):
                 ("e2_off", ctypes.c_int32), ("feq_order", ctypes.c_int32),
                 ("gamma", ctypes.c_double), ("prandtl", ctypes.c_double),
                 ("mu", ctypes.c_double), ("sigma", ctypes.c_double),
-                ("sgn_eps", ctypes.c_double)]
+                ("sgn_eps", ctypes.c_double), ("wall_ux_lo", ctypes.c_double),
+                ("wall_ux_hi", ctypes.c_double), ("wall_theta", ctypes.c_double)]
 
 
 _lib = None
@@ -125,7 +126,7 @@ def van_albada(a, b):
     return lib().ora_van_albada(a, b)
 
 
-BC = {"periodic": 0, "extrapolate": 1}
+BC = {"periodic": 0, "extrapolate": 1, "wall": 2}
 PHI = {"lbm": 0, "fd": 1}
 
 
@@ -144,11 +145,17 @@ class OracleParams:
     e2_off: bool = False
     feq_order: int = 4
     sgn_eps: float = 1e-12
+    # bc_y = "wall": velocities along x of the walls y = 0 and y = ny - 1, and
+    # their temperature
+    wall_ux_lo: float = 0.0
+    wall_ux_hi: float = 0.0
+    wall_theta: float = 1.0
 
     def c(self):
         return _Params(self.nx, self.ny, BC[self.bc_x], BC[self.bc_y], PHI[self.phi_mode],
                        int(self.e1_centred), int(self.e2_off), int(self.feq_order),
-                       self.gamma, self.prandtl, self.mu, self.sigma, self.sgn_eps)
+                       self.gamma, self.prandtl, self.mu, self.sigma, self.sgn_eps,
+                       self.wall_ux_lo, self.wall_ux_hi, self.wall_theta)
 
 
 class OracleSolver:

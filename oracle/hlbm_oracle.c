@@ -35,7 +35,23 @@
  * band |u| <= sgn_eps (the literal sign is discontinuous at u = 0 and turns
  * rounding noise into O(dGamma) jumps at wave fronts); 5-point Laplacian for the Fourier term;
  * boundaries per axis either periodic or zero-gradient (ghost = copy of the
- * nearest interior node state).
+ * nearest interior node state), or, along y, two isothermal moving walls.
+ *
+ * Walls (the paper's thermal Couette flow of Sec. 4.4 cites its wall
+ * condition to an earlier paper without stating it; this is our own reading,
+ * a regularised wet-node wall).  The wall rows y = 0 and y = ny - 1 are nodes
+ * of the grid, H = ny - 1 apart, beyond which ghosts are zero-gradient.
+ * After every step each wall node is rebuilt from its wall velocity
+ * (U_wall, 0) and temperature theta_w:
+ *   rho_w = sum of the populations with c_y = 0 + twice the sum of those that
+ *           arrived from the interior (zero mass flux through the wall);
+ *   F_w   = f^eq(rho_w, U_wall, 0, theta_w) + fbar^1[a1FD] with a1FD from the
+ *           velocity gradient at the wall: zero along the wall, one-sided
+ *           second order across it, (-3 u_0 + 4 u_1 - u_2) / 2 from the new
+ *           velocities of the next two rows; psi is taken as zero there;
+ *   s_w   = c_v ln(theta_w / rho_w^(gamma - 1)).
+ * The collision at a wall node uses the projected stress alone (sigma = 1),
+ * which recovers that a1FD.
  *
  * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC
  */
@@ -55,13 +71,16 @@ static const double CS2v = 1.0 / 3.0;
 
 typedef struct {
   int32_t nx, ny;
-  int32_t bc_x, bc_y;   /* 0 periodic, 1 zero-gradient extrapolation */
+  int32_t bc_x, bc_y;   /* 0 periodic, 1 zero-gradient extrapolation; bc_y 2: walls */
   int32_t phi_mode;     /* 0: Phi from a1 (LBM), 1: Phi by finite differences */
   int32_t e1_centred;   /* ablation: 1 = centred E1 (original model) */
   int32_t e2_off;       /* ablation: 1 = no E2 term (original model) */
   int32_t feq_order;    /* 4 (present model) or 3 (original model) */
   double gamma, prandtl, mu, sigma;
   double sgn_eps;       /* |u| <= sgn_eps counts as sgn(u) = 0 in E1 (0: literal sign) */
+  /* bc_y = 2: wall rows y = 0 and y = ny - 1 move along x with wall_ux_lo /
+   * wall_ux_hi and are held at temperature wall_theta */
+  double wall_ux_lo, wall_ux_hi, wall_theta;
 } ora_params;
 
 /* ------------------------------------------------------------------------- */
@@ -296,6 +315,8 @@ static double *alloc_field(size_t n) { return (double *)calloc(n, sizeof(double)
 
 void *ora_create(const ora_params *p) {
   if (!p || p->nx < 1 || p->ny < 1) return NULL;
+  if (p->bc_x < 0 || p->bc_x > 1 || p->bc_y < 0 || p->bc_y > 2) return NULL;
+  if (p->bc_y == 2 && (p->ny < 4 || !(p->wall_theta > 0.0))) return NULL;
   init_tables();
   ora_state *S = (ora_state *)calloc(1, sizeof(ora_state));
   S->p = *p;
@@ -470,8 +491,11 @@ static void collide_pass(ora_state *S) {
       fd[0] = -tp * (2.0 * S->dxux[k] - div);
       fd[1] = -tp * (S->dyux[k] + S->dxuy[k]);
       fd[2] = -tp * (2.0 * S->dyuy[k] - div);
+      /* wall nodes: projection only (their populations carry the wall stress) */
+      const int wall_row = S->p.bc_y == 2 && (Y == GH || Y == GH + S->p.ny - 1);
+      const double sg = wall_row ? 1.0 : sig;
       double a1[3];
-      for (int j = 0; j < 3; ++j) a1[j] = sig * pr[j] + (1.0 - sig) * fd[j];
+      for (int j = 0; j < 3; ++j) a1[j] = sg * pr[j] + (1.0 - sg) * fd[j];
       S->a1xx[k] = a1[0];
       S->a1xy[k] = a1[1];
       S->a1yy[k] = a1[2];
@@ -584,6 +608,61 @@ static void derive(ora_state *S) {
   collide_pass(S);
 }
 
+/* Velocity of node (X, Y) from its populations. */
+static void node_velocity(const ora_state *S, size_t k, double *ux, double *uy) {
+  double r = 0.0, jx = 0.0, jy = 0.0;
+  for (int i = 0; i < Q; ++i) {
+    r += S->F[i][k];
+    jx += CXv[i] * S->F[i][k];
+    jy += CYv[i] * S->F[i][k];
+  }
+  *ux = jx / r;
+  *uy = jy / r;
+}
+
+/* Rebuild the two wall rows (see the header).  side 0: y = 0, whose
+ * populations with c_y = -1 came from the interior; side 1: y = ny - 1, c_y
+ * = +1.  Reads only rows 1, 2 and ny - 2, ny - 3 besides the wall rows. */
+static void wall_pass(ora_state *S) {
+  const int nx = S->p.nx, ny = S->p.ny, order = S->p.feq_order;
+  const double thw = S->p.wall_theta;
+  for (int X = GH; X < GH + nx; ++X) {
+    double Fnew[2][Q], snew[2];
+    for (int side = 0; side < 2; ++side) {
+      const int Yw = side == 0 ? GH : GH + ny - 1;
+      const int dir = side == 0 ? 1 : -1;              /* towards the interior */
+      const double U = side == 0 ? S->p.wall_ux_lo : S->p.wall_ux_hi;
+      const size_t kw = IX(S, X, Yw);
+      double rho = 0.0;
+      for (int i = 0; i < Q; ++i) {
+        if (CYv[i] == 0) rho += S->F[i][kw];
+        else if (CYv[i] == -dir) rho += 2.0 * S->F[i][kw];  /* arrived from the interior */
+      }
+      double u1x, u1y, u2x, u2y;
+      node_velocity(S, IX(S, X, Yw + dir), &u1x, &u1y);
+      node_velocity(S, IX(S, X, Yw + 2 * dir), &u2x, &u2y);
+      /* d/dy, one-sided second order; the wall-normal velocity is zero */
+      const double dyux = dir * (-3.0 * U + 4.0 * u1x - u2x) / 2.0;
+      const double dyuy = dir * (4.0 * u1y - u2y) / 2.0;
+      const double pw = rho * CS2v * thw;
+      const double tp = (S->p.mu / pw + 0.5) * pw;      /* taubar p */
+      const double div = dyuy;
+      const double axx = -tp * (0.0 - div), axy = -tp * dyux, ayy = -tp * (2.0 * dyuy - div);
+      double fe[Q], f1v[Q], a1full[6];
+      feq_point(rho, U, 0.0, thw, order, fe);
+      a1_recursion(axx, axy, ayy, U, 0.0, thw, a1full);
+      f1_point(a1full, order, f1v);
+      for (int i = 0; i < Q; ++i) Fnew[side][i] = fe[i] + f1v[i];
+      snew[side] = S->cv * log(thw / pow(rho, S->p.gamma - 1.0));
+    }
+    for (int side = 0; side < 2; ++side) {
+      const size_t kw = IX(S, X, side == 0 ? GH : GH + ny - 1);
+      for (int i = 0; i < Q; ++i) S->F[i][kw] = Fnew[side][i];
+      S->s[kw] = snew[side];
+    }
+  }
+}
+
 void ora_step(void *h, int nsteps) {
   ora_state *S = (ora_state *)h;
   for (int n = 0; n < nsteps; ++n) {
@@ -591,6 +670,7 @@ void ora_step(void *h, int nsteps) {
     stream_pass(S);
     entropy_pass(S);
     swap_buffers(S);
+    if (S->p.bc_y == 2) wall_pass(S);
     S->steps++;
   }
 }
@@ -628,6 +708,7 @@ void ora_init(void *h, const double *rho, const double *ux, const double *uy, co
       f1_point(a1full, order, f1v);
       for (int i = 0; i < Q; ++i) S->F[i][k] = fe[i] + f1v[i] - 0.5 * ps[i];
     }
+  if (S->p.bc_y == 2) wall_pass(S);
   S->steps = 0;
 }
 
