@@ -94,13 +94,15 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 2 GiB device copy (counter calibration)")
     ap.add_argument("--workload", default="turbulence8192",
-                    choices=["turbulence8192", "batch256", "closure", "vortex-map"],
+                    choices=["turbulence8192", "batch256", "closure", "vortex-map", "couette"],
                     help="batch256: the 256-domain batch (one persistent launch per step, "
                          "graph-replayed), reported as aggregate MLUPS of the domains still "
                          "active at the end; closure: the corrected coarse step of the "
                          "learned closure (8 x 256^2) and the network's training step; "
                          "vortex-map: the sigma x Mach isentropic-vortex study of Sec. 4.2 "
-                         "(200^2, 50 convective times, 11 x 11 runs plus the original model)")
+                         "(200^2, 50 convective times, 11 x 11 runs plus the original model); "
+                         "couette: the thermal Couette flow of Sec. 4.4 on the 2 x 100 "
+                         "channel to steady state, and the cost of walls on an 8192^2 channel")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -112,6 +114,8 @@ def main():
         return bench_closure(args)
     if args.workload == "vortex-map":
         return bench_vortex_map(args)
+    if args.workload == "couette":
+        return bench_couette(args)
 
     import numpy as np
     import torch
@@ -169,6 +173,7 @@ def main():
 
     del S
     torch.cuda.empty_cache()
+    stream_ref = copy_reference(n, dev)
     learned = None if args.no_learned else learned_closure()
     torch.cuda.empty_cache()
     cpu = None
@@ -185,8 +190,35 @@ def main():
                       "nx": n, "ny": n, "global_batch": 1, "parallelism": "none",
                       "tile_w": params.tile_w or "auto", "tile_h": params.tile_h or "auto",
                       "status_after": int(code)},
-           "roofline": roofline, "cpu_baseline": cpu, "learned_closure": learned}
+           "roofline": roofline, "cpu_baseline": cpu, "stream_reference": stream_ref,
+           "learned_closure": learned}
     print(json.dumps(out), flush=True)
+
+
+def copy_reference(n, dev):
+    """A library elementwise copy moving the step kernel's algorithmic bytes
+    (ten FP32 planes of n^2 read, ten written), as a practical-bandwidth
+    reference for the roofline fraction."""
+    import torch
+    a = torch.zeros(10, n * n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        torch.mul(a, 1.0001, out=b)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    reps = 10
+    for _ in range(reps):
+        torch.mul(a, 1.0001, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    gbs = 80.0 * n * n / (ms / 1e3) / 1e9
+    return {"kernel": "torch.mul elementwise copy, 10 planes in / 10 out", "ms": round(ms, 4),
+            "achieved": round(gbs, 1), "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def learned_closure():
@@ -320,6 +352,52 @@ def bench_vortex_map(args):
                                   "theta 240/1183, mu 1.5e-6, 50 convective times, "
                                   "Ma 0.3..1.3 x sigma 0..1 (+ original model at sigma 0)"},
            "map": summ, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
+def bench_couette(args):
+    """Thermal Couette flow (Sec. 4.4): the paper's 2 x 100 channel run to
+    steady state in FP64 and FP32, with the error of the temperature profile
+    against the closed form; then an 8192^2 FP32 channel with walls (linear
+    shear, theta 0.2) timed against the same grid with periodic rows, which
+    prices the wall pass."""
+    import numpy as np
+    import torch
+
+    from paper_2002_03644_amd import Params, Solver, studies
+    runs = {dt: studies.thermal_couette(ny=100, dtype=dt) for dt in ("f64", "f32")}
+    n, thw, steps = args.n, 0.2, max(args.steps // 5, 20)
+    eta = (np.arange(n, dtype=np.float64) / (n - 1))[:, None]
+    fields = (np.ones((n, n)), 0.1 * eta * np.ones((1, n)), np.zeros((n, n)),
+              np.full((n, n), thw))
+    rate = {}
+    for bc in ("wall", "periodic"):
+        S = Solver(Params(n, n, dtype="f32", mu=1e-3, bc_y=bc, wall_ux_hi=0.1, wall_theta=thw,
+                          theta_ref=thw), fields[0], fields[1], fields[2], theta=fields[3])
+        S.step(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.step(steps)
+        torch.cuda.synchronize()
+        rate[bc] = n * n * steps / (time.perf_counter() - t0) / 1e6
+        del S
+        torch.cuda.empty_cache()
+    r64 = runs["f64"]
+    out = {"metric": "thermal Couette 2 x 100: steps per second to steady state (FP64)",
+           "value": round(r64["steps"] / r64["seconds"], 1), "unit": "steps/s",
+           "n_gpus": 1, "steps": r64["steps"], "warmup": 0,
+           "ms_per_step": round(r64["seconds"] * 1e3 / r64["steps"], 5),
+           "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "thermal Couette flow, 2 x 100 channel, Ma 0.8, Pr 0.71, "
+                                  "gamma 1.4, sigma 0.9, T_w / T_r = 0.2, nu 0.1"},
+           "couette": {dt: {"theta_error_vs_closed_form": r["error"],
+                            "ux_error": r["ux_error"], "steps": r["steps"],
+                            "seconds": round(r["seconds"], 3)} for dt, r in runs.items()},
+           "walls_8192": {"mlups_walls": round(rate["wall"], 1),
+                          "mlups_periodic": round(rate["periodic"], 1),
+                          "steps": steps},
+           "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
 

@@ -49,7 +49,7 @@ typedef enum {
   HLBM_ENOMEM = -5       /* host allocation of the handle failed */
 } hlbm_status_code;
 
-typedef enum { HLBM_BC_PERIODIC = 0, HLBM_BC_EXTRAPOLATE = 1 } hlbm_bc;
+typedef enum { HLBM_BC_PERIODIC = 0, HLBM_BC_EXTRAPOLATE = 1, HLBM_BC_WALL = 2 } hlbm_bc;
 typedef enum { HLBM_F64 = 0, HLBM_F32 = 1 } hlbm_dtype;
 typedef enum { HLBM_PHI_LBM = 0, HLBM_PHI_FD = 1 } hlbm_phi;
 
@@ -60,7 +60,10 @@ typedef struct {
   int32_t bc_x, bc_y;   /* hlbm_bc on both sides of that axis: periodic wrap,
                            or zero-gradient extrapolation (the neighbour index
                            is clamped into the grid, so ghost nodes carry the
-                           full state of the nearest boundary node) */
+                           full state of the nearest boundary node); bc_y
+                           alone may also be HLBM_BC_WALL: the rows y = 0 and
+                           y = ny - 1 are isothermal walls moving along x
+                           (ny >= 4; see hlbm_step), ghosts beyond them clamp */
   int32_t dtype;        /* hlbm_dtype of every array passed in or out */
   int32_t phi_mode;     /* viscous heat Phi: HLBM_PHI_LBM = -(tau/taubar) a1 : grad u
                            (Eq. viscous heat discret), HLBM_PHI_FD = finite
@@ -82,6 +85,9 @@ typedef struct {
                            difference) for |u| <= sgn_eps.  0 is the literal sign,
                            which is discontinuous at u = 0; 1e-12 keeps
                            rounding-level velocities from flipping the stencil */
+  double wall_ux_lo;    /* bc_y = HLBM_BC_WALL: x velocity of the wall row y = 0 */
+  double wall_ux_hi;    /* bc_y = HLBM_BC_WALL: x velocity of the wall row y = ny - 1 */
+  double wall_theta;    /* bc_y = HLBM_BC_WALL: temperature of both walls, > 0 */
 } hlbm_params;
 
 typedef struct hlbm_handle hlbm_handle;
@@ -112,7 +118,15 @@ int hlbm_init(hlbm_handle **out, const hlbm_params *p, void *workspace, size_t w
               const void *rho, const void *ux, const void *uy, const void *s,
               hlbm_stream_t stream);
 
-/* Enqueue nsteps (>= 0) time steps (Sec. 3.5, steps 5-11).  Asynchronous. */
+/* Enqueue nsteps (>= 0) time steps (Sec. 3.5, steps 5-11).  Asynchronous.
+ * With bc_y = HLBM_BC_WALL every step (and hlbm_init) ends by rebuilding the
+ * two wall rows, a regularised wet-node wall (our reading of the wall
+ * condition of the thermal Couette case, Sec. 4.4, which the paper cites
+ * without stating): rho_w from the populations with c_y = 0 plus twice those
+ * that arrived from the interior; F = f^eq(rho_w, (wall_ux, 0), wall_theta) +
+ * f^1[a1FD] with the velocity gradient zero along the wall and one-sided
+ * second order across it, (-3 u_w + 4 u_1 - u_2) / 2; s from rho_w and
+ * wall_theta.  The collision at wall nodes uses sigma = 1. */
 int hlbm_step(hlbm_handle *h, int32_t nsteps, hlbm_stream_t stream);
 
 /* Write the macroscopic fields of the current state: rho = sum F,
@@ -172,8 +186,9 @@ int hlbm_entropy_from_theta(int32_t dtype, double gamma, const void *rho, const 
  * ------------------------------------------------------------------------ */
 typedef struct hlbm_batch hlbm_batch;
 
-/* Workspace bytes for `count` domains, or 0 if any parameter set is invalid
- * or the dtypes differ.  Host-only. */
+/* Workspace bytes for `count` domains, or 0 if any parameter set is invalid,
+ * has walls (bc_y = HLBM_BC_WALL is not available in batches) or the dtypes
+ * differ.  Host-only. */
 size_t hlbm_batch_workspace_bytes(const hlbm_params *params, int32_t count);
 
 /* Initialise every domain as hlbm_init does.  params: host array of `count`;

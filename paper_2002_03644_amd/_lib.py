@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhlbm.so")
 HLBM_OK, HLBM_WARN_CFL = 0, 1
 HLBM_EINVAL, HLBM_EWORKSPACE, HLBM_EHIP, HLBM_EDIVERGED, HLBM_ENOMEM = -1, -2, -3, -4, -5
 F64, F32 = 0, 1
-BC = {"periodic": 0, "extrapolate": 1}
+BC = {"periodic": 0, "extrapolate": 1, "wall": 2}
 PHI = {"lbm": 0, "fd": 1}
 
 
@@ -37,7 +37,8 @@ class CParams(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("prandtl", ctypes.c_double),
                 ("mu", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("rho_ref", ctypes.c_double), ("theta_ref", ctypes.c_double),
-                ("sgn_eps", ctypes.c_double)]
+                ("sgn_eps", ctypes.c_double), ("wall_ux_lo", ctypes.c_double),
+                ("wall_ux_hi", ctypes.c_double), ("wall_theta", ctypes.c_double)]
 
 
 _lib = None
@@ -148,13 +149,17 @@ class Params:
     tile_w: int = 0
     tile_h: int = 0
     sgn_eps: float = 1e-12
+    # bc_y = "wall": x velocities of the walls y = 0 and y = ny - 1, their temperature
+    wall_ux_lo: float = 0.0
+    wall_ux_hi: float = 0.0
+    wall_theta: float = 1.0
 
     def c(self) -> CParams:
         return CParams(self.nx, self.ny, BC[self.bc_x], BC[self.bc_y],
                        F64 if self.dtype == "f64" else F32, PHI[self.phi_mode],
                        int(self.e1_centred), int(self.e2_off), int(self.tile_w), int(self.tile_h),
                        self.gamma, self.prandtl, self.mu, self.sigma, self.rho_ref, self.theta_ref,
-                       self.sgn_eps)
+                       self.sgn_eps, self.wall_ux_lo, self.wall_ux_hi, self.wall_theta)
 
     @property
     def torch_dtype(self):

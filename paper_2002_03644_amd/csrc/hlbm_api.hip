@@ -90,8 +90,15 @@ hlbm::TileShape default_tile(const hlbm_params *p) {
   hlbm::TileShape t;
   // 128-column tiles with 32-row strips measured fastest at 8192^2 in FP32
   // (aligned row segments, 21 resident waves per CU).
-  t.bw = p->tile_w ? p->tile_w : 128;
+  // Small grids get narrower tiles and shorter strips (down to 4 rows) until
+  // about 1024 workgroups exist: a strip is swept serially, so a few tall
+  // strips would leave the chip idle and make the step latency-bound.
+  t.bw = p->tile_w ? p->tile_w : (p->nx <= 64 ? 64 : 128);
   int rows = p->tile_h ? p->tile_h : 32;
+  if (!p->tile_h) {
+    const long long nbx = (p->nx + t.bw - 1) / t.bw;
+    while (rows > 4 && nbx * ((p->ny + rows - 1) / rows) < 1024) rows /= 2;
+  }
   if (rows > p->ny) rows = p->ny;
   t.rows = rows;
   t.xcd_remap = 1;
@@ -116,6 +123,9 @@ void fill_domain(const hlbm_params *p, hlbm::HostDomain *d) {
   d->gm1 = g - 1.0;
   d->e2c = (2.0 + 2.0) / 2.0 - g;  // (D + 2) / D - gamma with D = 2
   d->gamma = g;
+  d->wall_u_lo = p->wall_ux_lo;
+  d->wall_u_hi = p->wall_ux_hi;
+  d->wall_theta = p->wall_theta;
   if (p->dtype == HLBM_F32) {
     d->rho_ref = p->rho_ref;
     d->theta_ref = p->theta_ref;
@@ -133,6 +143,13 @@ void fill_domain(const hlbm_params *p, hlbm::HostDomain *d) {
 __global__ void k_clear_words(unsigned *w, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) w[i] = 0u;
+}
+
+// Wall rows of a state buffer (nothing without walls).
+hipError_t apply_walls(hlbm_handle *h, void *state, hipStream_t st) {
+  if (h->p.bc_y != HLBM_BC_WALL) return hipSuccess;
+  return h->p.dtype == HLBM_F64 ? hlbm::f64::wall(h->dom, state, st)
+                                : hlbm::f32::wall(h->dom, state, st);
 }
 
 hipError_t run_reduce(hlbm_handle *h, double host[hlbm::kReduceVals], hipStream_t st) {
@@ -157,7 +174,11 @@ int hlbm_validate(const hlbm_params *p) {
   if (!p) return HLBM_EINVAL;
   if (p->nx < 1 || p->ny < 1) return HLBM_EINVAL;
   if ((long long)p->nx * (long long)p->ny * 9LL >= (1LL << 31)) return HLBM_EINVAL;
-  if (p->bc_x < 0 || p->bc_x > 1 || p->bc_y < 0 || p->bc_y > 1) return HLBM_EINVAL;
+  if (p->bc_x < 0 || p->bc_x > 1 || p->bc_y < 0 || p->bc_y > 2) return HLBM_EINVAL;
+  if (p->bc_y == HLBM_BC_WALL &&
+      (p->ny < 4 || !finite_pos(p->wall_theta) || !isfinite(p->wall_ux_lo) ||
+       !isfinite(p->wall_ux_hi)))
+    return HLBM_EINVAL;
   if (p->dtype != HLBM_F64 && p->dtype != HLBM_F32) return HLBM_EINVAL;
   if (p->phi_mode != HLBM_PHI_LBM && p->phi_mode != HLBM_PHI_FD) return HLBM_EINVAL;
   if (p->e1_centred < 0 || p->e1_centred > 1 || p->e2_off < 0 || p->e2_off > 1) return HLBM_EINVAL;
@@ -209,6 +230,7 @@ int hlbm_init(hlbm_handle **out, const hlbm_params *p, void *workspace, size_t w
     e = hlbm::f64::init(h->dom, rho, ux, uy, s, buf(h, 0), st);
   else
     e = hlbm::f32::init(h->dom, rho, ux, uy, s, buf(h, 0), st);
+  if (e == hipSuccess) e = apply_walls(h, buf(h, 0), st);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, st, status_word(h), 64);
     e = hipGetLastError();
@@ -236,6 +258,7 @@ int hlbm_step(hlbm_handle *h, int32_t nsteps, hlbm_stream_t stream) {
       e = hlbm::f64::step(h->dom, buf(h, h->cur), buf(h, h->cur ^ 1), status_word(h), h->tile, st);
     else
       e = hlbm::f32::step(h->dom, buf(h, h->cur), buf(h, h->cur ^ 1), status_word(h), h->tile, st);
+    if (e == hipSuccess) e = apply_walls(h, buf(h, h->cur ^ 1), st);
     if (e != hipSuccess) return HLBM_EHIP;
     h->cur ^= 1;
     h->steps++;
@@ -429,6 +452,7 @@ int batch_validate(const hlbm_params *p, int32_t count) {
   for (int k = 0; k < count; ++k) {
     if (hlbm_validate(&p[k]) != HLBM_OK) return HLBM_EINVAL;
     if (p[k].dtype != p[0].dtype) return HLBM_EINVAL;
+    if (p[k].bc_y == HLBM_BC_WALL) return HLBM_EINVAL;  // the batched step has no wall pass
   }
   return HLBM_OK;
 }

@@ -50,6 +50,7 @@ struct DomainArgs {
   real mu, sigma, lambda, inv_cv, gm1, e2c, gamma, sgn_eps;
   real rho_ref, theta_ref, log_rho_ref, s_ref;
   real fref[kQ];       // deviation reference populations (zero in the FP64 form)
+  real wall_u_lo, wall_u_hi, wall_theta;  // bcy == kBcWall: wall velocities, temperature
 };
 
 struct StepArgs {
@@ -63,6 +64,7 @@ struct StepArgs {
 };
 
 constexpr int kFlagPhiFD = 1, kFlagE1Centred = 2, kFlagE2Off = 4;
+constexpr int kBcWall = 2;  // rows y = 0 and y = ny - 1 are walls (ghosts beyond them clamp)
 
 // ---------------------------------------------------------------- helpers
 __device__ __forceinline__ int map_index(int v, int n, int bc) {
@@ -313,7 +315,7 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
   __syncthreads();
 
   for (int i = 0; i < nit; ++i) {
-    // ---------------- issue the loads of row i+1 (consumed by A at the end)
+    // ---------------- issue the loads of row i+1 (consumed by A after B)
     real ld[kPlanes];
     const bool do_a = a_lane && i + 1 < nit;
     if (do_a) {
@@ -367,7 +369,11 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
         const real tp = taub * p;
         const real fdxx = -tp * (dxux - dyuy);
         const real fdxy = -tp * (dyux + dxuy);
-        const real sg = d.sigma, sg1 = real(1) - d.sigma;
+        // wall rows take the projected stress alone: their rebuilt populations
+        // carry the wall's finite-difference stress
+        const int yk = y0 - 2 + k;
+        const bool wall_row = d.bcy == kBcWall && (yk == 0 || yk == d.ny - 1);
+        const real sg = wall_row ? real(1) : d.sigma, sg1 = real(1) - sg;
         const real a1xx = sg * prxx + sg1 * fdxx;
         const real a1yy = sg * pryy - sg1 * fdxx;
         const real a1xy = sg * prxy + sg1 * fdxy;
@@ -415,6 +421,11 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
     }
     __syncthreads();
 
+    // ---------------- A(i+1) on the loads issued at the top.  It runs before
+    // C so that waiting for those loads never waits for C's stores as well
+    // (A writes ring slots of row i+1, which C does not read).
+    if (do_a) stage_a(i + 1, ld);
+
     // ---------------- C(k), k = i-2: stream and entropy
     if (i >= 4 && own_col) {
       const int k = i - 2;
@@ -449,9 +460,6 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
     cB_rho = nB_rho;
     cB_th = nB_th;
     cB_phi = nB_phi;
-
-    // ---------------- A(i+1) on the loads issued at the top
-    if (do_a) stage_a(i + 1, ld);
     __syncthreads();
   }
   if (bad) atomicOr(status, 1u);
@@ -581,6 +589,96 @@ __global__ void k_init(InitArgs a) {
     for (int q = 0; q < kQ; ++q) a.dst[q * P + o] = f[q];
     a.dst[9 * P + o] = a.s[i] - d.s_ref;
   }
+}
+
+// ------------------------------------------------------------ walls
+//
+// Isothermal moving walls on the rows y = 0 and y = ny - 1 (bcy == kBcWall),
+// a regularised wet-node wall: our reading of the wall condition that the
+// thermal Couette case of Sec. 4.4 takes from an earlier paper without
+// stating it.  After every step (and after initialisation) each wall node is
+// rebuilt as f^eq(rho_w, U, 0, theta_w) + f^1[a1FD], psi taken as zero, with
+//   rho_w = its c_y = 0 populations plus twice those that arrived from the
+//           interior (no mass flux through the wall);
+//   a1FD  from the velocity gradient at the wall: zero along it, one-sided
+//         second order across it, (-3 u_w + 4 u_1 - u_2) / 2 over the new
+//         velocities of the next two rows;
+//   s_w   = c_v ln(theta_w / rho_w^(gamma - 1)).
+// One thread per wall node, in place: a thread reads its node and two rows
+// of the interior, which no thread writes (ny >= 4).
+struct WallArgs {
+  DomainArgs d;
+  real *state;  // plane 0 of the current state
+};
+
+__device__ __forceinline__ void wall_node(const WallArgs &a, const int t) {
+  const DomainArgs &d = a.d;
+  const int side = t >= d.nx ? 1 : 0;
+  const int x = t - side * d.nx;
+  const int yw = side ? d.ny - 1 : 0, dir = side ? -1 : 1;
+  const real U = side ? d.wall_u_hi : d.wall_u_lo;
+  const long long P = d.plane;
+  real *node = a.state + (long long)yw * d.nx + x;
+  real F[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) F[q] = node[q * P];
+  // arrived from the interior: c_y = -1 (4, 7, 8) at y = 0, c_y = +1 (2, 5, 6) at the top;
+  // the rest state's share of the sum is exactly rho_ref, so this is rho_w - rho_ref
+  const real in = side ? (F[2] + F[5]) + F[6] : (F[4] + F[7]) + F[8];
+  const real dr = ((F[0] + F[1]) + F[3]) + real(2) * in;
+  const real rho = dr + d.rho_ref;
+  auto velocity = [&](int y, real &ux, real &uy) {
+    const real *p = a.state + (long long)y * d.nx + x;
+    real G[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) G[q] = p[q * P];
+    const NodeMoments m = node_moments(G, d);
+    ux = m.jx / m.rho;
+    uy = m.jy / m.rho;
+  };
+  real u1x, u1y, u2x, u2y;
+  velocity(yw + dir, u1x, u1y);
+  velocity(yw + 2 * dir, u2x, u2y);
+  const real half = real(0.5) * real(dir);
+  const real dyux = half * ((real(4) * u1x - u2x) - real(3) * U);
+  const real dyuy = half * (real(4) * u1y - u2y);
+  const real cs2 = real(kCs2);
+  const real th = d.wall_theta;
+  const real p = rho * cs2 * th;
+  const real tp = (d.mu / p + real(0.5)) * p;  // taubar p
+  // a1FD = -taubar p (grad u + grad u^T - div I) with d/dx = 0 and div = dyuy
+  const real a1xx = tp * dyuy, a1yy = -a1xx, a1xy = -tp * dyux;
+  const real c = cs2 * (th - real(1));
+  const real a1xxy = real(2) * U * a1xy;
+  const real a1xyy = U * a1yy;
+  const real a1xxyy = real(2) * U * a1xyy + (c - U * U) * a1yy + c * a1xx;
+  // deviations from the rest reference formed from deviations (theta_w is
+  // exact, so nothing cancels): rho c - rho_ref c_ref = (p - p_ref) - cs2
+  // (rho - rho_ref), rho c^2 - rho_ref c_ref^2 = dr c^2 + rho_ref dc (c + c_ref)
+  const real rc = rho * c;
+  const real cref = cs2 * (d.theta_ref - real(1));
+  const real dth = th - d.theta_ref;
+  const real dp = cs2 * (dr * th + d.rho_ref * dth);
+  const real drc = dp - cs2 * dr;
+  const real drc2 = dr * c * c + d.rho_ref * (cs2 * dth) * (c + cref);
+  const real Axx = rho * U * U + drc + a1xx;
+  const real Ayy = drc + a1yy;
+  const real Axy = a1xy;
+  const real Axxy = a1xxy;
+  const real Axyy = rc * U + a1xyy;
+  const real Axxyy = rc * U * U + drc2 + a1xxyy;
+  real f[kQ];
+  project(dr, rho * U, real(0), Axx, Axy, Ayy, Axxy, Axyy, Axxyy, f);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) node[q * P] = f[q];
+  // s_w - s_ref = c_v (ln(theta_w / theta_ref) - (gamma - 1) ln(rho_w / rho_ref))
+  node[9 * P] = (log_r(th) - log_r(d.theta_ref) - d.gm1 * (log_r(rho) - d.log_rho_ref)) / d.inv_cv;
+}
+
+__global__ void k_wall(WallArgs a) {
+  const int n = 2 * a.d.nx;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+    wall_node(a, t);
 }
 
 // ------------------------------------------------------------ moments

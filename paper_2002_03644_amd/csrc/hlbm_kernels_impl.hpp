@@ -28,6 +28,9 @@ static DomainArgs to_device(const HostDomain &h) {
   d.log_rho_ref = (real)h.log_rho_ref;
   d.s_ref = (real)h.s_ref;
   for (int q = 0; q < kQ; ++q) d.fref[q] = (real)h.fref[q];
+  d.wall_u_lo = (real)h.wall_u_lo;
+  d.wall_u_hi = (real)h.wall_u_hi;
+  d.wall_theta = (real)h.wall_theta;
   return d;
 }
 
@@ -62,6 +65,14 @@ hipError_t step(const HostDomain &h, const void *src, void *dst, unsigned *statu
   default:
     return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t wall(const HostDomain &h, void *state, hipStream_t st) {
+  WallArgs a;
+  a.d = to_device(h);
+  a.state = (real *)state;
+  hipLaunchKernelGGL(k_wall, dim3(grid_for(2LL * h.nx, 256)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

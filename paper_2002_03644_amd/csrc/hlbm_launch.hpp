@@ -14,6 +14,7 @@ struct HostDomain {
   double mu, sigma, lambda, inv_cv, gm1, e2c, gamma, sgn_eps;
   double rho_ref, theta_ref, log_rho_ref, s_ref;
   double fref[9];
+  double wall_u_lo, wall_u_hi, wall_theta;  // bcy == 2 (walls)
 };
 
 struct TileShape {
@@ -28,6 +29,7 @@ struct TileShape {
                   const TileShape &tile, hipStream_t st);                                   \
   hipError_t init(const HostDomain &d, const void *rho, const void *ux, const void *uy,     \
                   const void *s, void *dst, hipStream_t st);                                \
+  hipError_t wall(const HostDomain &d, void *state, hipStream_t st);                        \
   hipError_t moments(const HostDomain &d, const void *state, void *rho, void *ux, void *uy, \
                      void *s, void *theta, hipStream_t st);                                 \
   hipError_t populations(const HostDomain &d, void *state, void *F9, const void *s,         \

@@ -159,3 +159,51 @@ def acoustic_pulse(n=201, R=6.0, amp_pa=10.0, p_inf_pa=101323.0, t_frac=0.4, gam
                      "y0": float(n // 2), "u": mach * c, "steps": steps, "sigma": sigma,
                      "amp": p_inf * amp_pa / p_inf_pa, "c": c, "R": R}
     return out
+
+
+def couette_exact(eta, ma, pr, gamma):
+    """Steady temperature of the thermal Couette flow between walls at one
+    temperature T_w (Sec. 4.4): (T - T_w) / T_w = eta Pr Ma^2 (gamma - 1) / 2
+    (1 - eta), eta = y / H, Ma = U / c at T_w."""
+    eta = np.asarray(eta, dtype=np.float64)
+    return eta * pr * ma * ma * (gamma - 1.0) / 2.0 * (1.0 - eta)
+
+
+def thermal_couette(ny=100, nx=2, ma=0.8, pr=0.71, gamma=1.4, sigma=0.9, theta_w=300.0 / 1500.0,
+                    nu=0.1, steps=None, dtype="f64", phi_mode="lbm", device="cuda"):
+    """The thermal Couette flow of Sec. 4.4 on an nx x ny channel (the paper
+    uses 2 x 100, T_r = 1500 K, T_w = 300 K, sigma 0.9): periodic in x, walls
+    at the rows y = 0 (at rest) and y = ny - 1 (moving at U = Ma c_w, c_w the
+    sound speed at theta_w), both at theta_w.  Starts from the steady velocity
+    U y / H at uniform theta_w and density 1 and runs `steps` steps (default:
+    enough for the slowest thermal mode, decaying as exp(-pi^2 nu t / (Pr
+    H^2)), to fall below 1e-7).  Returns the theta and u_x profiles (FP64
+    numpy, averaged over x), the closed-form profiles, and the largest
+    temperature error relative to the largest temperature rise."""
+    import torch
+    from ._lib import Solver
+    H = ny - 1
+    c = hi.sound_speed(gamma, theta_w)
+    U = ma * c
+    if steps is None:
+        steps = int(np.ceil(1.7 * H * H * max(pr, 1.0) / nu))
+    eta = np.arange(ny, dtype=np.float64) / H
+    ones = np.ones((ny, nx))
+    p = Params(nx, ny, dtype=dtype, gamma=gamma, prandtl=pr, mu=nu, sigma=sigma, bc_y="wall",
+               wall_ux_lo=0.0, wall_ux_hi=U, wall_theta=theta_w, theta_ref=theta_w,
+               phi_mode=phi_mode)
+    S = Solver(p, ones, U * eta[:, None] * ones, 0.0 * ones, theta=theta_w * ones, device=device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.step(steps)
+    torch.cuda.synchronize()
+    seconds = time.perf_counter() - t0
+    m = {k: v.double().cpu().numpy() for k, v in S.moments().items()}
+    theta = m["theta"].mean(axis=1)
+    ux = m["ux"].mean(axis=1)
+    rise = couette_exact(eta, ma, pr, gamma)
+    exact = theta_w * (1.0 + rise)
+    err = float(np.abs(theta - exact).max() / (theta_w * rise.max()))
+    return {"theta": theta, "theta_exact": exact, "ux": ux, "ux_exact": U * eta, "error": err,
+            "ux_error": float(np.abs(ux - U * eta).max() / U), "steps": steps,
+            "seconds": seconds, "U": U, "nx": nx, "ny": ny}

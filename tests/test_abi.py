@@ -58,6 +58,28 @@ def test_validate_rejects(bad):
     assert workspace_bytes(p) == 0
 
 
+def test_wall_parameters_validated_on_the_host():
+    from paper_2002_03644_amd import HLBM_EINVAL, HLBM_OK, validate
+    ok = dict(bc_y="wall", wall_theta=0.2, wall_ux_hi=0.1)
+    assert validate(_params(**ok)) == HLBM_OK
+    assert validate(_params(ny=4, **ok)) == HLBM_OK
+    for bad in (dict(ny=3), dict(wall_theta=0.0), dict(wall_theta=float("inf")),
+                dict(wall_ux_lo=float("nan"))):
+        kw = dict(ok)
+        kw.update(bad)
+        assert validate(_params(**kw)) == HLBM_EINVAL, bad
+    assert validate(_params(bc_x="wall", wall_theta=0.2)) == HLBM_EINVAL  # walls along y only
+
+
+def test_batches_reject_walls():
+    import ctypes
+    from paper_2002_03644_amd import _lib
+    ps = [_params(), _params(bc_y="wall", wall_theta=0.2)]
+    arr = (_lib.CParams * 2)(*[p.c() for p in ps])
+    assert _lib.lib().hlbm_batch_workspace_bytes(arr, 1) > 0
+    assert _lib.lib().hlbm_batch_workspace_bytes(arr, 2) == 0
+
+
 def test_workspace_size_covers_two_state_buffers():
     from paper_2002_03644_amd import workspace_bytes
     for dt, es in (("f32", 4), ("f64", 8)):
