@@ -30,13 +30,18 @@ METRIC = ("HLBM MLUPS & % HBM roofline @8192² FP32; learned-vs-plain time at eq
           "error")
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
 BYTES_PER_NODE = 80            # read 9 populations + s, write 9 + s, FP32
-KERNEL_SRC = os.path.join(ROOT, "paper_2002_03644_amd", "csrc", "hlbm_device.hpp")
+# sources that decide the step kernel and its launch shape (tile defaults)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2002_03644_amd", "csrc", f)
+               for f in ("hlbm_device.hpp", "hlbm_kernels_impl.hpp", "hlbm_api.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_f32_turbulence8192_traffic.txt")
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(nodes: int):

@@ -72,7 +72,7 @@ typedef struct {
                            1: centred E1 (original-model ablation) */
   int32_t e2_off;       /* 0: with the polyatomic E2 term (present model);
                            1: without it (original-model ablation) */
-  int32_t tile_w;       /* tile width in columns (64, 128 or 256; the workgroup has
+  int32_t tile_w;       /* tile width in columns (64, 128, 192 or 256; the workgroup has
                            tile_w + 64 lanes, the extra wave holds the halo), 0 = auto */
   int32_t tile_h;       /* output rows per workgroup strip (>= 1), 0 = auto */
   double gamma;         /* heat-capacity ratio, > 1 */

@@ -59,6 +59,9 @@ hipError_t step(const HostDomain &h, const void *src, void *dst, unsigned *statu
   case 128:
     hipLaunchKernelGGL(k_step<128>, dim3(nblk), dim3(128 + 64), 0, st, a);
     break;
+  case 192:
+    hipLaunchKernelGGL(k_step<192>, dim3(nblk), dim3(192 + 64), 0, st, a);
+    break;
   case 256:
     hipLaunchKernelGGL(k_step<256>, dim3(nblk), dim3(256 + 64), 0, st, a);
     break;

@@ -154,7 +154,7 @@ def test_tile_shape_invariance(dtype):
     r, u, v, t = hi.vortex(nx, ny, 150, 48, 9, 0.9, 0.3, noise=1e-4, seed=1)
     s = oracle.entropy_from_theta(r, t, 1.4)
     outs = []
-    for tw, th in ((64, 8), (128, 32), (256, 5), (64, 97), (128, 1)):
+    for tw, th in ((64, 8), (128, 32), (256, 5), (64, 97), (128, 1), (192, 16), (192, 7)):
         G = Solver(Params(nx, ny, dtype=dtype, mu=1e-3, sigma=0.3, tile_w=tw, tile_h=th),
                    r, u, v, s=s)
         G.step(25)
