@@ -190,31 +190,37 @@ __device__ __forceinline__ real muscl_term(real u, real sm2, real sm1, real s0, 
 //   A(j)    moments of row j from the ten planes: u, theta, Gamma and s go
 //           into LDS rings, rho and Pi stay in registers;
 //   B(k)    gradients, E, a1 and the nine post-collision populations of row
-//           k (radius-1 stencil through the rings) into an LDS ring;
-//   C(k)    pull streaming of row k out of that ring and its entropy update
+//           k (radius-1 stencil through the rings): the six with c_x != 0
+//           into LDS rings, the three with c_x = 0 into the lane's registers;
+//   C(k)    pull streaming of row k out of those and its entropy update
 //           (radius-2 stencil), storing both.
-// Iteration i issues the loads of row i+1, runs B(i-1), a barrier, C(i-2),
-// then A(i+1) on the loads issued at its top, and a second barrier.  Loads are
-// thus consumed in the iteration that issued them, after the B and C work
-// that hides their latency.  Each node's moments and collision are computed
-// once per step (plus a 4-column halo); HBM sees one read and one write of
-// the state.
+// Iteration i issues the loads of row i+1, runs B(i-1), a barrier, A(i+1) on
+// those loads, C(i-2), and a second barrier.  Loads are thus consumed in the
+// iteration that issued them, after the B work that hides their latency, and
+// before C's stores (a wait placed after stores that sit under a branch
+// would also wait for the stores).  Each node's moments and collision are
+// computed once per step (plus a 4-column halo); HBM sees one read and one
+// write of the state.
 //
 // Ring depths are the smallest the two barriers per iteration allow (only a
 // write of A(i+1) may overlap a read of C(i-2) of another wave):
 //   u_x, u_y, Gamma_y: 3 rows (B reads rows k-1..k+1);  Gamma_x: 2 (row k);
 //   theta: 5 (C reads rows k-1 and k+1);  s: 6 (C reads rows k-2..k+2);
 //   post-collision populations by the row they stream from: c_y = 0 -> 2,
-//   c_y = +1 (read one row later) -> 3, c_y = -1 (read in the same row) -> 1.
+//   c_y = +1 (read one row later) -> 3, c_y = -1 (read in the same row) -> 1;
+//   in registers the same delays: population 0 one row, 2 two rows, 4 none.
+// 34 rows of CW + 4 floats in all: 26.7 KB at CW = 192, six workgroups per CU.
 // Shared memory of one tile sweep.
 template <int CW>
 struct TileRings {
   static constexpr int W = CW + 4;  // ring width: tile plus halo
   real ux[3][W], uy[3][W], gy[3][W], gx[2][W];
   real th[5][W], s[6][W];
-  real f0[2][3][W];  // populations 0, 1, 3   (c_y =  0)
-  real fp[3][3][W];  // populations 2, 5, 6   (c_y = +1)
-  real fm[3][W];     // populations 4, 7, 8   (c_y = -1)
+  // post-collision populations that stream across columns; 0, 2 and 4
+  // (c_x = 0) stay in their lane's registers
+  real f0[2][2][W];  // populations 1, 3   (c_y =  0)
+  real fp[3][2][W];  // populations 5, 6   (c_y = +1)
+  real fm[2][W];     // populations 7, 8   (c_y = -1)
 };
 
 // One tile (bx, by) of one domain: src / dst point at plane 0 of the two
@@ -269,6 +275,9 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
   // iteration, read by C(k) in the next one.
   real nB_ux = 0, nB_uy = 0, nB_rho = 1, nB_th = 1, nB_phi = 0;
   real cB_ux = 0, cB_uy = 0, cB_rho = 1, cB_th = 1, cB_phi = 0;
+  // populations 0, 2, 4 of B's rows kept in registers: nB_* of row k (this
+  // iteration's B), cB_f0 of row k-1, cB_f2 of row k-1, cB_f2b of row k-2
+  real nB_f0 = 0, nB_f2 = 0, nB_f4 = 0, cB_f0 = 0, cB_f2 = 0, cB_f2b = 0;
 
   // A(j): moments of one row from its ten loaded planes.
   auto stage_a = [&](const int j, const real (&ld)[kPlanes]) {
@@ -396,15 +405,15 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
         const real Axxyy = ruxx * uy * uy + rc * (ux * ux + uy * uy) + drc2 + om * a1xxyy;
         real f[kQ];
         project(s0_dr, rux, ruy, Axx, Axy, Ayy, Axxy, Axyy, Axxyy, f);
-        r_f0[k & 1][0][ri] = f[0];
-        r_f0[k & 1][1][ri] = f[1];
-        r_f0[k & 1][2][ri] = f[3];
-        r_fp[sc][0][ri] = f[2];
-        r_fp[sc][1][ri] = f[5];
-        r_fp[sc][2][ri] = f[6];
-        r_fm[0][ri] = f[4];
-        r_fm[1][ri] = f[7];
-        r_fm[2][ri] = f[8];
+        r_f0[k & 1][0][ri] = f[1];
+        r_f0[k & 1][1][ri] = f[3];
+        r_fp[sc][0][ri] = f[5];
+        r_fp[sc][1][ri] = f[6];
+        r_fm[0][ri] = f[7];
+        r_fm[1][ri] = f[8];
+        nB_f0 = f[0];
+        nB_f2 = f[2];
+        nB_f4 = f[4];
         real phi;
         if (d.flags & kFlagPhiFD) {
           const real aa = dxux - dyuy, bb = dyux + dxuy;
@@ -431,15 +440,15 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
       const int k = i - 2;
       const int z = k & 1, pm = (k + 2) % 3;  // slot of row k in r_f0, of row k-1 in r_fp
       real Fo[kQ];
-      Fo[0] = r_f0[z][0][ri];
-      Fo[1] = r_f0[z][1][ri - 1];
-      Fo[3] = r_f0[z][2][ri + 1];
-      Fo[2] = r_fp[pm][0][ri];
-      Fo[5] = r_fp[pm][1][ri - 1];
-      Fo[6] = r_fp[pm][2][ri + 1];
-      Fo[4] = r_fm[0][ri];
-      Fo[7] = r_fm[1][ri + 1];
-      Fo[8] = r_fm[2][ri - 1];
+      Fo[0] = cB_f0;    // row k, this column
+      Fo[1] = r_f0[z][0][ri - 1];
+      Fo[3] = r_f0[z][1][ri + 1];
+      Fo[2] = cB_f2b;   // row k-1, this column
+      Fo[5] = r_fp[pm][0][ri - 1];
+      Fo[6] = r_fp[pm][1][ri + 1];
+      Fo[4] = nB_f4;    // row k+1, this column
+      Fo[7] = r_fm[0][ri + 1];
+      Fo[8] = r_fm[1][ri - 1];
       const int s0 = k % 6, s1 = (k + 1) % 6, s2 = (k + 2) % 6, sm1 = (k + 5) % 6,
                 sm2 = (k + 4) % 6;
       const real sc = r_s[s0][ri];
@@ -460,6 +469,9 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
     cB_rho = nB_rho;
     cB_th = nB_th;
     cB_phi = nB_phi;
+    cB_f2b = cB_f2;
+    cB_f2 = nB_f2;
+    cB_f0 = nB_f0;
     __syncthreads();
   }
   if (bad) atomicOr(status, 1u);
