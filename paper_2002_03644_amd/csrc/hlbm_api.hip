@@ -477,11 +477,11 @@ hipError_t batch_upload_items(hlbm_batch *b, int tw, int th, hipStream_t st) {
                                           : hlbm::f32::batch_blocks_per_cu(tw);
   b->grid = std::max(1, std::min(b->nitems, per_cu * b->ncu));
   if (b->graph) {
-    hipGraphExecDestroy(b->graph);
+    (void)hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
   }
   if (b->cgraph) {
-    hipGraphExecDestroy(b->cgraph);
+    (void)hipGraphExecDestroy(b->cgraph);
     b->cgraph = nullptr;
   }
   return hipSuccess;
@@ -589,7 +589,7 @@ int hlbm_batch_step(hlbm_batch *b, int32_t nsteps, int32_t use_graph, hlbm_strea
   if (use_graph && n >= 2) {
     if (!b->graph || b->graph_cur != b->cur) {
       if (b->graph) {
-        hipGraphExecDestroy(b->graph);
+        (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
       }
       hipGraph_t g = nullptr;
@@ -599,11 +599,11 @@ int hlbm_batch_step(hlbm_batch *b, int32_t nsteps, int32_t use_graph, hlbm_strea
       hipError_t e2 = batch_launch(b, b->cur ^ 1, st);
       e = hipStreamEndCapture(st, &g);
       if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return HLBM_EHIP;
       }
       e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       if (e != hipSuccess) {
         b->graph = nullptr;
         return HLBM_EHIP;
@@ -675,7 +675,7 @@ int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, int32_t *host_best_w, int3
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return HLBM_EHIP;
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return HLBM_EHIP;
   }
   int rc = HLBM_OK;
@@ -683,12 +683,12 @@ int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, int32_t *host_best_w, int3
     for (int th : hs) {
       if (batch_upload_items(b, tw, th, st) != hipSuccess) { rc = HLBM_EHIP; break; }
       if (hlbm_batch_step(b, 1, 0, st) != HLBM_OK) { rc = HLBM_EHIP; break; }
-      hipEventRecord(e0, st);
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = HLBM_EHIP; break; }
       if (hlbm_batch_step(b, steps, 0, st) != HLBM_OK) { rc = HLBM_EHIP; break; }
-      hipEventRecord(e1, st);
+      if (hipEventRecord(e1, st) != hipSuccess) { rc = HLBM_EHIP; break; }
       if (hipEventSynchronize(e1) != hipSuccess) { rc = HLBM_EHIP; break; }
       float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = HLBM_EHIP; break; }
       if (ms < best) {
         best = ms;
         bw = tw;
@@ -697,8 +697,8 @@ int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, int32_t *host_best_w, int3
     }
     if (rc != HLBM_OK) break;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc != HLBM_OK) return rc;
   if (batch_upload_items(b, bw, bh, st) != hipSuccess) return HLBM_EHIP;
   if (host_best_w) *host_best_w = bw;
@@ -733,8 +733,8 @@ int64_t hlbm_batch_steps_done(const hlbm_batch *b) { return b ? b->steps : -1; }
 
 void hlbm_batch_destroy(hlbm_batch *b) {
   if (!b) return;
-  if (b->graph) hipGraphExecDestroy(b->graph);
-  if (b->cgraph) hipGraphExecDestroy(b->cgraph);
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  if (b->cgraph) (void)hipGraphExecDestroy(b->cgraph);
   delete b;
 }
 
@@ -805,7 +805,7 @@ int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t ncycles, int32_t every
         b->cgraph_conserve != conserve || b->cgraph_version != hlbm_cnn_version(c) ||
         b->cgraph_every != every) {
       if (b->cgraph) {
-        hipGraphExecDestroy(b->cgraph);
+        (void)hipGraphExecDestroy(b->cgraph);
         b->cgraph = nullptr;
       }
       const int cur0 = b->cur;
@@ -817,11 +817,11 @@ int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t ncycles, int32_t every
       hipError_t e = hipStreamEndCapture(st, &g);
       b->cur = cur0;   // capture only recorded the launches
       if (rc1 != HLBM_OK || rc2 != HLBM_OK || e != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return HLBM_EHIP;
       }
       e = hipGraphInstantiate(&b->cgraph, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       if (e != hipSuccess) {
         b->cgraph = nullptr;
         return HLBM_EHIP;
