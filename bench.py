@@ -419,7 +419,11 @@ def bench_batch(args):
     fields = [hi.batch_domain_fields(sp) for sp in specs]
     B = BatchSolver(params, fields)
     del fields
-    tw, th = B.autotune(steps=3)
+    if args.tile_w and args.tile_h:
+        B.set_tile(args.tile_w, args.tile_h)
+        tw, th = args.tile_w, args.tile_h
+    else:
+        tw, th = B.autotune(steps=10)
     B.step(args.warmup, graph=True)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)

@@ -393,7 +393,7 @@ struct hlbm_batch {
 
 namespace {
 
-constexpr int kBatchTileW[3] = {64, 128, 256};
+constexpr int kBatchTileW[4] = {64, 128, 192, 256};
 constexpr int kBatchMinRows = 8;
 
 int batch_items_for(const hlbm_batch *b, int tw, int th, std::vector<int> *out) {
@@ -660,7 +660,7 @@ int hlbm_batch_status(hlbm_batch *b, int32_t *host_flags, hlbm_stream_t stream) 
 
 int hlbm_batch_set_tile(hlbm_batch *b, int32_t tile_w, int32_t tile_h, hlbm_stream_t stream) {
   if (!b) return HLBM_EINVAL;
-  if (tile_w != 64 && tile_w != 128 && tile_w != 256) return HLBM_EINVAL;
+  if (tile_w != 64 && tile_w != 128 && tile_w != 192 && tile_w != 256) return HLBM_EINVAL;
   if (tile_h < kBatchMinRows) return HLBM_EINVAL;
   return hip_status(batch_upload_items(b, tile_w, tile_h, (hipStream_t)stream));
 }

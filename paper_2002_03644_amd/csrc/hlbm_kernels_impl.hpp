@@ -167,6 +167,9 @@ hipError_t step_batch(const void *doms, const long long *offs, const void *items
   case 128:
     hipLaunchKernelGGL(k_step_batch<128>, dim3(grid), dim3(128 + 64), 0, st, a);
     break;
+  case 192:
+    hipLaunchKernelGGL(k_step_batch<192>, dim3(grid), dim3(192 + 64), 0, st, a);
+    break;
   case 256:
     hipLaunchKernelGGL(k_step_batch<256>, dim3(grid), dim3(256 + 64), 0, st, a);
     break;
@@ -225,6 +228,7 @@ int batch_blocks_per_cu(int cw) {
   hipError_t e = hipErrorInvalidValue;
   if (cw == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch<64>, 128, 0);
   if (cw == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch<128>, 192, 0);
+  if (cw == 192) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch<192>, 256, 0);
   if (cw == 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch<256>, 320, 0);
   return e == hipSuccess && n > 0 ? n : 1;
 }

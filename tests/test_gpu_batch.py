@@ -2,6 +2,7 @@
 
 Per-node arithmetic is the single-domain kernel's, so a batched run must be
 bitwise identical to running each domain alone with the same tile shape."""
+import dataclasses
 import json
 import os
 
@@ -47,14 +48,18 @@ def singles(params, fields, steps):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("graph", [False, True])
-def test_batch_bitwise_equals_single_domains(dtype, graph):
+@pytest.mark.parametrize("graph,tile", [(False, (128, 32)), (True, (128, 32)),
+                                        (True, (192, 16))])
+def test_batch_bitwise_equals_single_domains(dtype, graph, tile):
     params, fields = domain_set(dtype)
     B = BatchSolver(params, fields)
-    B.set_tile(128, 32)
+    B.set_tile(*tile)
     B.step(23, graph=graph)
     mb = B.moments()
-    ms = singles(params, fields, 23)
+    # FP32 FMA placement may differ between kernels compiled for different
+    # widths, so the single-domain reference uses the batch's tile
+    ms = singles([dataclasses.replace(p, tile_w=tile[0], tile_h=tile[1]) for p in params],
+                 fields, 23)
     for k in range(len(params)):
         for key in ("rho", "ux", "uy", "s"):
             assert torch.equal(mb[k][key], ms[k][key]), (k, key)
@@ -102,7 +107,7 @@ def test_autotune_restores_state_and_caches(tmp_path):
     before = [m["rho"].clone() for m in B.moments()]
     cache = str(tmp_path / "tune.json")
     w, h = B.autotune(steps=2, cache_path=cache)
-    assert w in (64, 128, 256) and h in (8, 16, 32, 64, 128)
+    assert w in (64, 128, 192, 256) and h in (8, 16, 32, 64, 128)
     after = [m["rho"] for m in B.moments()]
     for a, b in zip(before, after):
         assert torch.equal(a, b)
