@@ -73,14 +73,27 @@ def cpu_baseline(n_sample=1024, steps=150):
     S = oracle.OracleSolver(oracle.OracleParams(n_sample, n_sample, mu=1e-3, sigma=0.0),
                             r, u, v, theta=t)
     S.step(1)
+    cores = oracle.threads()
     t0 = time.perf_counter()
     S.step(steps)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    del S
+    # one thread, on a 256^2 window of the same recipe
+    n1, steps1 = 256, 30
+    r, u, v, t = hi.turbulence(n1, 0.5, hi.THETA_PAPER, seed=0)
+    S1 = oracle.OracleSolver(oracle.OracleParams(n1, n1, mu=1e-3, sigma=0.0), r, u, v, theta=t)
+    oracle.threads(1)
+    S1.step(1)
+    t1 = time.perf_counter()
+    S1.step(steps1)
+    dt1 = time.perf_counter() - t1
+    oracle.threads(cores)
     return {"value": round(n_sample * n_sample * steps / dt / 1e6, 3), "unit": "MLUPS",
             "cores": cores, "kind": "oracle",
             "sample": f"{n_sample}x{n_sample} periodic window of the same turbulence recipe, "
-                      f"{steps} steps after 1 warm-up step, FP64, {dt:.1f} s"}
+                      f"{steps} steps after 1 warm-up step, FP64, {dt:.1f} s",
+            "single_thread": {"value": round(n1 * n1 * steps1 / dt1 / 1e6, 3), "unit": "MLUPS",
+                              "sample": f"{n1}x{n1} window, {steps1} steps, {dt1:.1f} s"}}
 
 
 def main():
@@ -286,7 +299,7 @@ def bench_closure(args):
         fields.append(tuple(np.ascontiguousarray(a[::f, ::f]) for a in (r, u, v, t)))
         params.append(L._params(nc, setup.mu_coarse, float(t[0, 0]), setup))
     B = BatchSolver(params, fields)
-    tw, th = B.autotune(steps=5)
+    tw, th = B.autotune(steps=10)
     net = CNN(len(seeds), nc, nc, L.initial_params(0))
     net.set_norm(np.array([1, 0, 0, 0.2], np.float32), np.array([0.1, 0.1, 0.1, 0.01], np.float32),
                  np.zeros(4, np.float32), np.array([1e-3, 1e-3, 1e-3, 1e-4], np.float32))

@@ -74,6 +74,8 @@ def lib():
         L.ora_van_albada.argtypes = [ctypes.c_double, ctypes.c_double]
         L.ora_van_albada.restype = ctypes.c_double
         L.ora_entropy.argtypes = [P, P, ctypes.c_double, ctypes.c_long, P]
+        L.ora_threads.argtypes = [ctypes.c_int]
+        L.ora_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -81,6 +83,12 @@ def lib():
 def _ptr(a: np.ndarray):
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def threads(n: int = 0) -> int:
+    """Threads of the oracle's OpenMP passes: n > 0 sets them; returns the
+    count in effect."""
+    return int(lib().ora_threads(int(n)))
 
 
 def entropy_from_theta(rho, theta, gamma):

@@ -59,6 +59,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define Q 9
 #define GH 2 /* ghost depth = stencil radius */
@@ -835,4 +838,16 @@ double ora_van_albada(double a, double b) { return van_albada(a, b); }
 void ora_entropy(const double *rho, const double *theta, double gamma, long n, double *s) {
   double cv = CS2v / (gamma - 1.0);
   for (long j = 0; j < n; ++j) s[j] = cv * log(theta[j] / pow(rho[j], gamma - 1.0));
+}
+
+/* Threads of the OpenMP passes: n > 0 sets the count for later calls; the
+ * return value is the count in effect (1 without OpenMP). */
+int ora_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }

@@ -440,7 +440,7 @@ class BatchSolver:
         key = ";".join(f"{p.nx}x{p.ny}:{p.dtype}" for p in self.params)
         return hashlib.sha256(key.encode()).hexdigest()[:20]
 
-    def autotune(self, steps=3, cache_path=None):
+    def autotune(self, steps=10, cache_path=None):
         """Pick the fastest tile shape by timing (state restored afterwards).
         With ``cache_path`` the choice is read from / written to a JSON file
         keyed by the batch's domain sizes and dtype."""

@@ -383,12 +383,12 @@ def evaluate(net: CNN, setup: ClosureSetup, seeds=None, ladder=None, judge=None,
     if timing:
         # every arm on its fastest tile shape (the autotuner restores the state)
         B = make_c()
-        B.autotune(steps=5)
+        B.autotune(steps=10)
         learned(B, 4)
         t_learned = _time(lambda: learned(B, steps), B.stream)
         del B
         B = make_c()
-        B.autotune(steps=5)
+        B.autotune(steps=10)
         plain(B, 4)
         t_plain[nc] = _time(lambda: plain(B, steps), B.stream)
         del B
@@ -396,7 +396,7 @@ def evaluate(net: CNN, setup: ClosureSetup, seeds=None, ladder=None, judge=None,
             pm = [_params(N, setup.mu_fine * N / nf, th, setup) for th in thetas]
             fl = [fine0[s] for s in seeds] if N == nf else _ladder_fields(seeds, N, setup, fine0)
             B = BatchSolver(pm, fl, device=device)
-            B.autotune(steps=3)
+            B.autotune(steps=10)
             plain(B, 4)
             t_plain[N] = _time(lambda: plain(B, steps * N // nc), B.stream)
             del B

@@ -70,7 +70,7 @@ def sigma_mach_map(machs=None, sigmas=None, n=200, conv_times=50.0, beta=0.1, mu
                          e1_centred=(m == "original"), e2_off=(m == "original"))
                   for m, s in models]
         B = BatchSolver(params, [f] * len(models), device=device)
-        B.autotune(steps=3)
+        B.autotune(steps=10)
         B.step(steps, graph=True)
         _, flags = B.status()
         mom = B.moments()
