@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
 BYTES_PER_NODE = 80            # read 9 populations + s, write 9 + s, FP32
 # sources that decide the step kernel and its launch shape (tile defaults)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2002_03644_amd", "csrc", f)
-               for f in ("hlbm_device.hpp", "hlbm_kernels_impl.hpp", "hlbm_api.hip")]
+               for f in ("hlbm_device.hpp", "hlbm_launch.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_f32_turbulence8192_traffic.txt")
 
 

@@ -87,25 +87,7 @@ void rest_equilibrium(double rho, double theta, double f[9]) {
 }
 
 hlbm::TileShape default_tile(const hlbm_params *p) {
-  hlbm::TileShape t;
-  // 192-column tiles with 16-row strips measured fastest at 8192^2 in FP32:
-  // the extra halo wave is a quarter of the workgroup instead of a third
-  // (the sweep is bound by instruction issue as much as by HBM), the row
-  // segments stay 256-byte aligned, and 16-row strips beat taller ones.
-  // Grids narrower than 1536 columns keep 128-column tiles (less ragged).
-  // Small grids get narrower tiles and shorter strips (down to 4 rows) until
-  // about 1024 workgroups exist: a strip is swept serially, so a few tall
-  // strips would leave the chip idle and make the step latency-bound.
-  t.bw = p->tile_w ? p->tile_w : (p->nx <= 64 ? 64 : (p->nx >= 1536 ? 192 : 128));
-  int rows = p->tile_h ? p->tile_h : (t.bw == 192 ? 16 : 32);
-  if (!p->tile_h) {
-    const long long nbx = (p->nx + t.bw - 1) / t.bw;
-    while (rows > 4 && nbx * ((p->ny + rows - 1) / rows) < 1024) rows /= 2;
-  }
-  if (rows > p->ny) rows = p->ny;
-  t.rows = rows;
-  t.xcd_remap = 1;
-  return t;
+  return hlbm::step_tile(p->nx, p->ny, p->tile_w, p->tile_h);
 }
 
 void fill_domain(const hlbm_params *p, hlbm::HostDomain *d) {

@@ -1,4 +1,4 @@
-// Host-side launch interface between the C ABI (hlbm_api.cpp) and the
+// Host-side launch interface between the C ABI (hlbm_api.hip) and the
 // per-precision kernel translation units.  Internal to the library.
 #pragma once
 
@@ -18,10 +18,33 @@ struct HostDomain {
 };
 
 struct TileShape {
-  int bw;        // tile width in columns (64, 128 or 256); workgroup = bw + 64 lanes
+  int bw;        // tile width in columns (64, 128, 192 or 256); workgroup = bw + 64 lanes
   int rows;      // output rows per strip
   int xcd_remap; // 0 or 1
 };
+
+// Tile shape of the single-domain step for an nx x ny grid; tile_w, tile_h
+// > 0 are taken as given.
+//  - 192-column tiles with 16-row strips measured fastest at 8192^2 in FP32
+//    (row segments stay 256-byte aligned, the halo wave is a quarter of the
+//    workgroup, 16-row strips beat taller ones); grids narrower than 1536
+//    columns keep 128-column tiles with 32-row strips (less ragged).
+//  - Small grids get 64-column tiles (nx <= 64) and strips halved down to 4
+//    rows until about 1024 workgroups exist: a strip is swept serially, so a
+//    few tall strips would leave the chip idle.
+inline TileShape step_tile(int nx, int ny, int tile_w, int tile_h) {
+  TileShape t;
+  t.bw = tile_w ? tile_w : (nx <= 64 ? 64 : (nx >= 1536 ? 192 : 128));
+  int rows = tile_h ? tile_h : (t.bw == 192 ? 16 : 32);
+  if (!tile_h) {
+    const long long nbx = (nx + t.bw - 1) / t.bw;
+    while (rows > 4 && nbx * ((ny + rows - 1) / rows) < 1024) rows /= 2;
+  }
+  if (rows > ny) rows = ny;
+  t.rows = rows;
+  t.xcd_remap = 1;
+  return t;
+}
 
 #define HLBM_DECLARE_LAUNCHERS(NS)                                                          \
   namespace NS {                                                                            \
