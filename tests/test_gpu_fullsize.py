@@ -74,11 +74,12 @@ def patch_check(S, params, samples, steps_before, tol_F, tol_s, bc_x="periodic")
 
 
 def test_f32_turbulence_8192_sampled_one_step():
-    """Decaying turbulence 8192^2, FP32, default tiles (as bench.py): after 20
-    steps, one more GPU step matches the oracle's step of the same FP32 state
-    on 80 patches -- random nodes plus tile seams (x = 127, 128), strip seams
-    (y = 31, 32) and the periodic corners.  FP32 arithmetic: 1e-6 on F
-    (values ~0.01-0.4), 2e-6 on s (|s| ~ 1.3)."""
+    """Decaying turbulence 8192^2, FP32, default tiles (as bench.py: 192 x 16,
+    the last tile column ragged at x = 8064): after 20 steps, one more GPU
+    step matches the oracle's step of the same FP32 state on 88 patches --
+    random nodes plus tile seams (x = 191, 192, 8063, 8064), strip seams
+    (y = 15, 16), the 128 x 32 seams and the periodic corners.  FP32
+    arithmetic: 1e-6 on F (values ~0.01-0.4), 2e-6 on s (|s| ~ 1.3)."""
     n = 8192
     r, u, v, t = hi.turbulence(n, 0.5, hi.THETA_PAPER, seed=0)
     params = Params(n, n, dtype="f32", mu=1e-3, sigma=0.0)
@@ -91,7 +92,9 @@ def test_f32_turbulence_8192_sampled_one_step():
     samples = [(int(a), int(b)) for a, b in rng.integers(0, n, size=(64, 2))]
     samples += [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (31, 127), (32, 128),
                 (31, 128), (32, 127), (4095, 4096), (4096, 4095), (n - 33, 255), (5, 8191),
-                (8191, 3), (100, 128 * 40), (32 * 200, 77), (32 * 255 + 31, 128 * 63 + 127)]
+                (8191, 3), (100, 128 * 40), (32 * 200, 77), (32 * 255 + 31, 128 * 63 + 127),
+                (15, 191), (16, 192), (15, 192), (16, 191), (16 * 300 + 15, 8063),
+                (16 * 300 + 16, 8064), (8191, 8064), (16 * 511 + 15, 192 * 41 + 191)]
     patch_check(S, params, samples, 20, tol_F=1e-6, tol_s=2e-6)
 
 
@@ -109,5 +112,6 @@ def test_f64_mach2_2048x512_sampled_one_step():
     samples = [(int(a), int(b)) for a, b in zip(rng.integers(0, ny, 24),
                                                 rng.integers(0, nx, 24))]
     samples += [(10, 0), (20, 1), (30, nx - 1), (40, nx - 2), (0, 1024), (511, 1023),
-                (31, 127), (32, 128), (200, 1020), (201, 1030)]
+                (31, 127), (32, 128), (200, 1020), (201, 1030), (15, 191), (16, 192),
+                (300, 1919), (301, 1920)]
     patch_check(S, params, samples, 50, tol_F=1e-13, tol_s=1e-13, bc_x="extrapolate")
