@@ -62,6 +62,43 @@ def measured_traffic(nodes: int):
         return None
 
 
+def gpu_same_window(oracle_mlups, n=1024, steps=150):
+    """The GPU library on the oracle's sample (the same 1024^2 window of the
+    turbulence recipe, 150 steps), FP32 and FP64, for a side-by-side ratio."""
+    import torch
+
+    import hlbm_inputs as hi
+    from paper_2002_03644_amd import Params, Solver
+    r, u, v, t = hi.turbulence(n, 0.5, hi.THETA_PAPER, seed=0)
+    out = {}
+    for dt in ("f32", "f64"):
+        S = Solver(Params(n, n, dtype=dt, mu=1e-3, sigma=0.0), r, u, v, theta=t)
+        S.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.step(steps)
+        torch.cuda.synchronize()
+        out[f"{dt}_mlups"] = round(n * n * steps / (time.perf_counter() - t0) / 1e6, 1)
+        del S
+    out["f64_over_oracle"] = round(out["f64_mlups"] / oracle_mlups, 1)
+    out["f32_over_oracle"] = round(out["f32_mlups"] / oracle_mlups, 1)
+    out["sample"] = f"{n}x{n} window, {steps} steps, default tiles"
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_model() -> str:
+    """Host CPU model name (Linux), or 'unknown'."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n_sample=1024, steps=150):
     """The FP64 oracle on an n_sample^2 periodic window of the same
     turbulence recipe, timed on the host cores (steady-state steps only)."""
@@ -89,7 +126,7 @@ def cpu_baseline(n_sample=1024, steps=150):
     dt1 = time.perf_counter() - t1
     oracle.threads(cores)
     return {"value": round(n_sample * n_sample * steps / dt / 1e6, 3), "unit": "MLUPS",
-            "cores": cores, "kind": "oracle",
+            "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{n_sample}x{n_sample} periodic window of the same turbulence recipe, "
                       f"{steps} steps after 1 warm-up step, FP64, {dt:.1f} s",
             "single_thread": {"value": round(n1 * n1 * steps1 / dt1 / 1e6, 3), "unit": "MLUPS",
@@ -192,12 +229,14 @@ def main():
     del S
     torch.cuda.empty_cache()
     stream_ref = copy_reference(n, dev)
+    stream_ref["step_frac_of_copy"] = round(achieved / stream_ref["achieved"], 4)
     learned = None if args.no_learned else learned_closure()
     torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu = cpu_baseline()
+        cpu["gpu_same_window"] = gpu_same_window(cpu["value"])
 
     out = {"metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
