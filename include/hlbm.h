@@ -209,12 +209,12 @@ int hlbm_batch_moments(hlbm_batch *b, void *rho, void *ux, void *uy, void *s, vo
  * diverged domains (>= 0) or an error.  Synchronises `stream`. */
 int hlbm_batch_status(hlbm_batch *b, int32_t *host_flags, hlbm_stream_t stream);
 
-/* Tile shape of the batched kernel: tile_w in {64, 128, 192, 256}, tile_h >= 8.
+/* Tile shape of the batched kernel: tile_w in {64, 128, 192, 256}, tile_h >= 4.
  * Synchronises `stream`. */
 int hlbm_batch_set_tile(hlbm_batch *b, int32_t tile_w, int32_t tile_h, hlbm_stream_t stream);
 
-/* Time `steps` steps for every tile shape in {64, 128, 192, 256} x {8, 16, 32,
- * 64, 128}, keep the fastest and report it.  Advances the domains; save and load
+/* Time `steps` steps for every tile shape in {64, 128, 192, 256} x {4, 8, 16,
+ * 32, 64, 128}, keep the fastest and report it.  Advances the domains; save and load
  * the state around it to keep them.  Synchronises `stream`. */
 int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, int32_t *host_best_w, int32_t *host_best_h,
                         hlbm_stream_t stream);

@@ -376,7 +376,7 @@ struct hlbm_batch {
 namespace {
 
 constexpr int kBatchTileW[4] = {64, 128, 192, 256};
-constexpr int kBatchMinRows = 8;
+constexpr int kBatchMinRows = 4;  // short strips: small domains are bound by the serial sweep
 
 int batch_items_for(const hlbm_batch *b, int tw, int th, std::vector<int> *out) {
   // largest domains first: the round-robin walk then ends on small items
@@ -651,7 +651,7 @@ int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, int32_t *host_best_w, int3
                         hlbm_stream_t stream) {
   if (!b || steps < 1) return HLBM_EINVAL;
   hipStream_t st = (hipStream_t)stream;
-  const int hs[5] = {8, 16, 32, 64, 128};
+  const int hs[6] = {4, 8, 16, 32, 64, 128};
   float best = 1e30f;
   int bw = b->tile_w, bh = b->tile_h;
   hipEvent_t e0, e1;

@@ -107,7 +107,7 @@ def test_autotune_restores_state_and_caches(tmp_path):
     before = [m["rho"].clone() for m in B.moments()]
     cache = str(tmp_path / "tune.json")
     w, h = B.autotune(steps=2, cache_path=cache)
-    assert w in (64, 128, 192, 256) and h in (8, 16, 32, 64, 128)
+    assert w in (64, 128, 192, 256) and h in (4, 8, 16, 32, 64, 128)
     after = [m["rho"] for m in B.moments()]
     for a, b in zip(before, after):
         assert torch.equal(a, b)
