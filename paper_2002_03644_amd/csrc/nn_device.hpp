@@ -301,9 +301,12 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
 // four strips covering columns 8..71, is exact.  The standardised input rows
 // y0-3 .. y0+rows+2 are staged in LDS first, so the row loop issues no global
 // loads.  Layer rows stream through four-row rings: at step j the workgroup
-// computes layer-1 row y0+j-3, layer-2 row y0+j-5 and output row y0+j-7,
-// each from rows the previous three steps completed, with one barrier per
-// step.  Each wave has one role, which balances the matrix-core work (about
+// computes layer-1 row y0+j-3 and completes layer-2 row y0+j-5 and output
+// row y0+j-7, with one barrier per step.  Layers 2 and 3 read only the
+// newest row of their input ring (three fragments per strip) and add its
+// three tap rows to the three output rows it touches, whose accumulators
+// rotate; each row still sums its taps in the order t = 0..8.  Each wave has
+// one role, which balances the matrix-core work (about
 // 36 MFMAs per wave and step) and keeps only that role's weights in
 // registers:
 //   wave 0: layer 2, strips 0 and 1      wave 2: layer 2, strip 4, and layer 1
@@ -397,6 +400,8 @@ __global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) bias1[nb][r] = a.b1[16 * nb + 4 * g + r];
     }
+    // layer-2 rows in progress per strip: a2m one tap row short, a2o two
+    f32x4 a2m[2][2] = {}, a2o[2][2] = {};
     for (int j = 1; j <= R + 6; ++j) {
       __syncthreads();
       if (wave == 2 && j <= R + 4) {     // layer 1, row y0 + j - 3: tile rows j-1+dy
@@ -425,22 +430,42 @@ __global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
           for (int nb = 0; nb < 2; ++nb) relu_store(&l1_ring[j & 3][col][16 * nb + 4 * g], acc[nb]);
         }
       }
-      if (j >= 4 && j <= R + 5) {        // layer 2, row y0 + j - 5
-        for (int st = s0; st < s0 + ns; ++st) {
-          const int col = 16 * st + n;
-          bf16x8 bv[9];
+      if (j >= 2 && j <= R + 5) {
+        // layer 2: the newest layer-1 row y0 + j - 4 (written at step j - 1)
+        // is read once and gives its tap row dy = 0 to layer-2 row y0 + j - 3
+        // (started from the bias), dy = 1 to row y0 + j - 4 and dy = 2 to row
+        // y0 + j - 5, which is then complete.  Each row still accumulates its
+        // taps in the order t = 0 .. 8.
+        const int slot = (j - 1) & 3;
 #pragma unroll
-          for (int t = 0; t < 9; ++t)
-            bv[t] = *(const bf16x8 *)&l1_ring[(j + 5 + t / 3) & 3][clampc(col + t % 3 - 1)][8 * g];
-          // all nine reads in flight before the first MFMA waits on one
-          __builtin_amdgcn_sched_barrier(0);
-          f32x4 acc[2] = {bias2[0], bias2[1]};
+        for (int si = 0; si < 2; ++si) {
+          if (si < ns) {
+            const int col = 16 * (s0 + si) + n;
+            bf16x8 bv[3];
 #pragma unroll
-          for (int t = 0; t < 9; ++t)
+            for (int dx = 0; dx < 3; ++dx)
+              bv[dx] = *(const bf16x8 *)&l1_ring[slot][clampc(col + dx - 1)][8 * g];
+            __builtin_amdgcn_sched_barrier(0);
+            f32x4 an[2] = {bias2[0], bias2[1]};
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb) acc[nb] = mfma(w2[t][nb], bv[t], acc[nb]);
+            for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
-          for (int nb = 0; nb < 2; ++nb) relu_store(&l2_ring[j & 3][col][16 * nb + 4 * g], acc[nb]);
+              for (int nb = 0; nb < 2; ++nb) {
+                an[nb] = mfma(w2[dx][nb], bv[dx], an[nb]);
+                a2m[si][nb] = mfma(w2[3 + dx][nb], bv[dx], a2m[si][nb]);
+                a2o[si][nb] = mfma(w2[6 + dx][nb], bv[dx], a2o[si][nb]);
+              }
+            if (j >= 4) {
+#pragma unroll
+              for (int nb = 0; nb < 2; ++nb)
+                relu_store(&l2_ring[j & 3][col][16 * nb + 4 * g], a2o[si][nb]);
+            }
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+              a2o[si][nb] = a2m[si][nb];
+              a2m[si][nb] = an[nb];
+            }
+          }
         }
       }
     }
@@ -452,21 +477,35 @@ __global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
     f32x4 bias3;
 #pragma unroll
     for (int r = 0; r < 4; ++r) bias3[r] = (4 * g + r < kOut) ? a.b3[4 * g + r] : 0.f;
+    // output rows in progress per strip: a3m one tap row short, a3o two
+    f32x4 a3m[4] = {}, a3o[4] = {};
     for (int j = 1; j <= R + 6; ++j) {
       __syncthreads();
-      if (j < 7) continue;
+      if (j < 5) continue;
+      // the newest layer-2 row y0 + j - 6 (written at step j - 1) gives tap
+      // row dy = 0 to output row y0 + j - 5, dy = 1 to y0 + j - 6 and dy = 2
+      // to y0 + j - 7, which is then complete
+      const int slot = (j - 1) & 3;
       const long long row = (long long)(y0 + j - 7) * W;
+#pragma unroll
       for (int st = 0; st < 4; ++st) {
         const int col = 8 + 16 * st + n;
-        bf16x8 bv[9];
+        bf16x8 bv[3];
 #pragma unroll
-        for (int t = 0; t < 9; ++t)
-          bv[t] = *(const bf16x8 *)&l2_ring[(j + 5 + t / 3) & 3][col + t % 3 - 1][8 * g];
+        for (int dx = 0; dx < 3; ++dx)
+          bv[dx] = *(const bf16x8 *)&l2_ring[slot][col + dx - 1][8 * g];
         __builtin_amdgcn_sched_barrier(0);
-        f32x4 acc = bias3;
+        f32x4 an = bias3;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) acc = mfma(w3[t], bv[t], acc);
-        if (g == 0) {
+        for (int dx = 0; dx < 3; ++dx) {
+          an = mfma(w3[dx], bv[dx], an);
+          a3m[st] = mfma(w3[3 + dx], bv[dx], a3m[st]);
+          a3o[st] = mfma(w3[6 + dx], bv[dx], a3o[st]);
+        }
+        const f32x4 acc = a3o[st];
+        a3o[st] = a3m[st];
+        a3m[st] = an;
+        if (j >= 7 && g == 0) {
           const long long i = row + x0 + col - 8;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
