@@ -115,3 +115,30 @@ def test_f64_mach2_2048x512_sampled_one_step():
                 (31, 127), (32, 128), (200, 1020), (201, 1030), (15, 191), (16, 192),
                 (300, 1919), (301, 1920)]
     patch_check(S, params, samples, 50, tol_F=1e-13, tol_s=1e-13, bc_x="extrapolate")
+
+
+@pytest.mark.parametrize("dtype,tol_F,tol_s", [("f64", 1e-13, 1e-13), ("f32", 1e-6, 2e-6)])
+def test_largest_grid_sampled_one_step(dtype, tol_F, tol_s):
+    """The largest grid the ABI accepts, 15446 x 15446 (9 nx ny just below
+    2^31; one FP64 plane is 1.9 GB, so byte offsets reach their limit):
+    after 2 steps, one more GPU step matches the oracle on patches at the
+    far corner, the last rows and columns, the middle and random nodes.
+    Smooth separable fields keep the host-side setup cheap."""
+    n = 15446
+    assert 9 * n * n < 2 ** 31 <= 9 * (n + 1) * (n + 1)
+    k = 2 * np.pi / n
+    xs, ys = np.arange(n), np.arange(n)
+    rho = 1.0 + 0.01 * np.outer(np.cos(3 * k * ys), np.sin(2 * k * xs))
+    ux = 0.05 + 0.02 * np.outer(np.sin(5 * k * ys), np.ones(n))
+    uy = 0.02 * np.outer(np.ones(n), np.cos(7 * k * xs))
+    theta = np.full((n, n), hi.THETA_PAPER)
+    params = Params(n, n, dtype=dtype, mu=1e-3, sigma=0.5)
+    S = Solver(params, rho, ux, uy, theta=theta)
+    del rho, ux, uy, theta
+    rng = np.random.default_rng(11)
+    samples = [(int(a), int(b)) for a, b in rng.integers(0, n, size=(8, 2))]
+    samples += [(n - 1, n - 1), (n - 2, n - 3), (n - 1, 0), (0, n - 1), (n // 2, n // 2),
+                (n - 7, 15000), (15000, n - 7), (0, 0)]
+    patch_check(S, params, samples, 2, tol_F=tol_F, tol_s=tol_s)
+    del S
+    torch.cuda.empty_cache()
