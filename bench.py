@@ -62,6 +62,33 @@ def measured_traffic(nodes: int):
         return None
 
 
+def f64_same_config(n, fields, tile_w, tile_h, steps=100):
+    """The same workload in FP64 (160 algorithmic bytes per node), timed over
+    `steps` steps after 5 warm-up steps, for context beside the FP32 line."""
+    import torch
+
+    from paper_2002_03644_amd import Params, Solver
+    r, u, v, t = fields
+    S = Solver(Params(n, n, dtype="f64", mu=1e-3, sigma=0.0, tile_w=tile_w, tile_h=tile_h),
+               r, u, v, theta=t)
+    S.step(5)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    S.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    code, _ = S.status()
+    del S
+    torch.cuda.empty_cache()
+    gbs = 2 * BYTES_PER_NODE * n * n / (ms / 1e3) / 1e9
+    return {"mlups": round(n * n / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 4),
+            "achieved": round(gbs, 1), "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "steps": steps, "status_after": int(code)}
+
+
 def gpu_same_window(oracle_mlups, n=1024, steps=150):
     """The GPU library on the oracle's sample (the same 1024^2 window of the
     turbulence recipe, 150 steps), FP32 and FP64, for a side-by-side ratio."""
@@ -142,6 +169,8 @@ def main():
     ap.add_argument("--tile-w", type=int, default=0)
     ap.add_argument("--tile-h", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f64", action="store_true",
+                    help="skip the FP64 run of the same workload (100 steps)")
     ap.add_argument("--map-dtype", default="f64", choices=["f32", "f64"],
                     help="precision of the vortex-map workload")
     ap.add_argument("--no-learned", action="store_true",
@@ -185,7 +214,6 @@ def main():
                     tile_h=args.tile_h)
     dev = torch.device("cuda:0")
     fields = [torch.from_numpy(a.astype(np.float32)).to(dev) for a in (r, u, v, t)]
-    del r, u, v, t
     S = Solver(params, *fields[:3], theta=fields[3], device=dev)
     del fields
     torch.cuda.synchronize()
@@ -230,6 +258,8 @@ def main():
     torch.cuda.empty_cache()
     stream_ref = copy_reference(n, dev)
     stream_ref["step_frac_of_copy"] = round(achieved / stream_ref["achieved"], 4)
+    f64 = None if args.no_f64 else f64_same_config(n, (r, u, v, t), args.tile_w, args.tile_h)
+    del r, u, v, t
     learned = None if args.no_learned else learned_closure()
     torch.cuda.empty_cache()
     cpu = None
@@ -248,6 +278,7 @@ def main():
                       "tile_w": params.tile_w or "auto", "tile_h": params.tile_h or "auto",
                       "status_after": int(code)},
            "roofline": roofline, "cpu_baseline": cpu, "stream_reference": stream_ref,
+           "f64": f64,
            "learned_closure": learned}
     print(json.dumps(out), flush=True)
 
