@@ -187,6 +187,30 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
+def _dev_buf(t, device, nbytes, dtype=None, what="buffer"):
+    """Check that a caller's tensor can back a raw device pointer of at least
+    nbytes bytes: a contiguous torch tensor on `device` (of `dtype` if given).
+    The ABI cannot check sizes itself, so a short buffer would be read or
+    written out of bounds."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor")
+    def norm(d):
+        d = torch.device(d)
+        if d.type == "cuda" and d.index is None:
+            d = torch.device("cuda", torch.cuda.current_device())
+        return d
+    if norm(t.device) != norm(device):
+        raise ValueError(f"{what}: on {t.device}, expected {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what}: dtype {t.dtype}, expected {dtype}")
+    if t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{what}: {t.numel() * t.element_size()} bytes, need {nbytes}")
+    return t
+
+
 def _dev_field(a, p: Params, device):
     import torch
     t = torch.as_tensor(a)
@@ -269,6 +293,9 @@ class Solver:
         import torch
         F = torch.as_tensor(F).to(self.device, self.p.torch_dtype).contiguous()
         s = torch.as_tensor(s).to(self.device, self.p.torch_dtype).contiguous()
+        n = self.p.nx * self.p.ny
+        if F.numel() != 9 * n or s.numel() != n:
+            raise ValueError("set_populations: F must hold 9 nx ny values and s nx ny")
         _check(lib().hlbm_set_populations(self.h, _ptr(F), _ptr(s), _stream()),
                "hlbm_set_populations")
 
@@ -292,6 +319,8 @@ class Solver:
         return buf
 
     def load_state(self, buf):
+        _dev_buf(buf, self.device, lib().hlbm_state_bytes(ctypes.byref(self._cp)),
+                 what="load_state")
         _check(lib().hlbm_load_state(self.h, _ptr(buf), _stream()), "hlbm_load_state")
 
 
@@ -371,6 +400,9 @@ class BatchSolver:
         n = int(self.offsets[-1])
         if out is None:
             out = torch.empty(len(keys), n, dtype=td, device=self.device)
+        elif tuple(out.shape) != (len(keys), n):
+            raise ValueError(f"moments_cat: out must be [{len(keys)}][{n}]")
+        _dev_buf(out, self.device, 0, td, "moments_cat out")
         cat = {k: out[j] for j, k in enumerate(keys)}
         self._enter()
         _check(lib().hlbm_batch_moments(self.h, _ptr(cat.get("rho")), _ptr(cat.get("ux")),
@@ -412,6 +444,7 @@ class BatchSolver:
         return buf
 
     def load_state(self, buf):
+        _dev_buf(buf, self.device, lib().hlbm_batch_state_bytes(self.h), what="load_state")
         self._enter()
         _check(lib().hlbm_batch_load_state(self.h, _ptr(buf), _stream(self.stream)),
                "hlbm_batch_load_state")
@@ -420,6 +453,9 @@ class BatchSolver:
     def correct(self, x, delta, conserve=True):
         """Apply increments ``delta`` to moments ``x`` (both [4][count][ny nx]
         float32 device tensors) of an FP32 batch of equal-size domains."""
+        import torch
+        for t, what in ((x, "correct x"), (delta, "correct delta")):
+            _dev_buf(t, self.device, 4 * self.nodes * 4, torch.float32, what)
         self._enter()
         _check(lib().hlbm_batch_correct(self.h, _ptr(x), _ptr(delta), int(bool(conserve)),
                                         _stream(self.stream)), "hlbm_batch_correct")

@@ -165,3 +165,21 @@ def test_nn_entry_points_validate_on_the_host():
     assert L.hlbm_restrict(fake, fake, fake, None, 1, 16, 16, 4, fake, 64, 16, None) == EINVAL
     assert L.hlbm_restrict(fake, fake, fake, fake, 1, 16, 16, 4, fake, 0, 16, None) == EINVAL
     assert L.hlbm_restrict(fake, fake, fake, fake, 0, 16, 16, 4, fake, 64, 16, None) == EINVAL
+
+
+def test_binding_rejects_buffers_the_abi_cannot_check():
+    """The ABI takes raw pointers, so the binding checks a caller's buffer
+    (type, device, contiguity, dtype, size) before passing it on."""
+    import numpy as np
+    import torch
+    from paper_2002_03644_amd._lib import _dev_buf
+    ok = torch.zeros(16, dtype=torch.float32)
+    assert _dev_buf(ok, "cpu", 64, torch.float32) is ok
+    with pytest.raises(TypeError):
+        _dev_buf(np.zeros(16, dtype=np.float32), "cpu", 64)
+    with pytest.raises(ValueError):
+        _dev_buf(ok, "cpu", 65)                                   # too short
+    with pytest.raises(ValueError):
+        _dev_buf(ok, "cpu", 64, torch.float64)                    # wrong dtype
+    with pytest.raises(ValueError):
+        _dev_buf(torch.zeros(8, 4)[:, ::2], "cpu", 16)            # not contiguous
