@@ -23,6 +23,32 @@ def _field_strides(t, ny, nx, what):
     return t.stride(0), t.stride(1)
 
 
+def _check_extent(t, sb, sc, nsamp, ny, nx, what):
+    """The kernels read or write element s sb + c sc + i (s < nsamp, c < 4,
+    i < ny nx) from t's first element on; all of it must lie in t's storage."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32:
+        raise ValueError(f"{what}: expected a float32 torch tensor")
+    avail = t.untyped_storage().nbytes() // t.element_size() - t.storage_offset()
+    need = (nsamp - 1) * sb + 3 * sc + ny * nx
+    if nsamp < 1 or sb < 0 or sc < 0 or need > avail:
+        raise ValueError(f"{what}: {nsamp} samples with strides ({sb}, {sc}) need {need} "
+                         f"elements, the tensor has {avail}")
+
+
+def _check_idx(idx, batch, device):
+    """idx: int32 device tensor of at least `batch` entries.  Its values must
+    be sample indices of x (and target); they are not read back here, which
+    would synchronise the stream on every training step."""
+    import torch
+    if idx is None:
+        return
+    if not isinstance(idx, torch.Tensor) or idx.dtype != torch.int32 or not idx.is_contiguous():
+        raise ValueError("idx: expected a contiguous int32 torch tensor")
+    if idx.device.type != torch.device(device).type or idx.numel() < batch:
+        raise ValueError(f"idx: needs {batch} entries on the network's device")
+
+
 def _f32(t, device):
     import torch
     return torch.as_tensor(t).to(device=device, dtype=torch.float32).contiguous()
@@ -96,6 +122,12 @@ class CNN:
             return int(sstride), int(cstride)
         return _field_strides(t, self.ny, self.nx, what)
 
+    def _check_pair(self, x, sb, sc, target, tsb, tsc, batch, idx):
+        _check_idx(idx, batch, self.device)
+        if idx is None:
+            _check_extent(x, sb, sc, batch, self.ny, self.nx, "x")
+            _check_extent(target, tsb, tsc, batch, self.ny, self.nx, "target")
+
     def forward(self, x, batch=None, idx=None, sstride=None, cstride=None, out=None):
         """Raw increments [batch][4][ny][nx] for the fields x."""
         import torch
@@ -104,6 +136,10 @@ class CNN:
         if out is None:
             out = torch.empty(batch, 4, self.ny, self.nx, dtype=torch.float32, device=self.device)
         osb, osc = _field_strides(out, self.ny, self.nx, "out")
+        _check_idx(idx, batch, self.device)
+        if idx is None:
+            _check_extent(x, sb, sc, batch, self.ny, self.nx, "x")
+        _check_extent(out, osb, osc, batch, self.ny, self.nx, "out")
         _check(lib().hlbm_cnn_forward(self.h, _ptr(x), sb, sc, _ptr(idx), batch, _ptr(out),
                                       osb, osc, _stream()), "hlbm_cnn_forward")
         return out
@@ -116,6 +152,7 @@ class CNN:
         batch = int(batch if batch is not None else (len(idx) if idx is not None else x.shape[0]))
         if loss is None:
             loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        self._check_pair(x, sb, sc, target, tsb, tsc, batch, idx)
         _check(lib().hlbm_cnn_loss_grad(self.h, _ptr(x), sb, sc, _ptr(target), tsb, tsc,
                                         _ptr(idx), batch, _ptr(loss), _stream()),
                "hlbm_cnn_loss_grad")
@@ -132,6 +169,7 @@ class CNN:
         batch = int(batch if batch is not None else (len(idx) if idx is not None else x.shape[0]))
         if loss is None:
             loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        self._check_pair(x, sb, sc, target, tsb, tsc, batch, idx)
         _check(lib().hlbm_cnn_train_step(self.h, _ptr(x), sb, sc, _ptr(target), tsb, tsc,
                                          _ptr(idx), batch, float(lr), _ptr(loss), _stream()),
                "hlbm_cnn_train_step")

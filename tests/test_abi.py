@@ -183,3 +183,23 @@ def test_binding_rejects_buffers_the_abi_cannot_check():
         _dev_buf(ok, "cpu", 64, torch.float64)                    # wrong dtype
     with pytest.raises(ValueError):
         _dev_buf(torch.zeros(8, 4)[:, ::2], "cpu", 16)            # not contiguous
+
+
+def test_network_binding_checks_field_extents_and_idx():
+    import torch
+    from paper_2002_03644_amd._nn import _check_extent, _check_idx
+    x = torch.zeros(3, 4, 8, 32)
+    _check_extent(x, 4 * 8 * 32, 8 * 32, 3, 8, 32, "x")
+    _check_extent(x[1:], 4 * 8 * 32, 8 * 32, 2, 8, 32, "x")       # a view: offset counted
+    with pytest.raises(ValueError):
+        _check_extent(x, 4 * 8 * 32, 8 * 32, 4, 8, 32, "x")       # one sample too many
+    with pytest.raises(ValueError):
+        _check_extent(x[1:], 4 * 8 * 32, 8 * 32, 3, 8, 32, "x")
+    with pytest.raises(ValueError):
+        _check_extent(x.double(), 4 * 8 * 32, 8 * 32, 1, 8, 32, "x")
+    _check_idx(None, 5, "cpu")
+    _check_idx(torch.zeros(5, dtype=torch.int32), 5, "cpu")
+    with pytest.raises(ValueError):
+        _check_idx(torch.zeros(4, dtype=torch.int32), 5, "cpu")    # too few entries
+    with pytest.raises(ValueError):
+        _check_idx(torch.zeros(5, dtype=torch.int64), 5, "cpu")    # wrong dtype
