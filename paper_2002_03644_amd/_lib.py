@@ -226,6 +226,8 @@ def entropy_from_theta(rho, theta, gamma, dtype="f64", device="cuda"):
     td = torch.float64 if dtype == "f64" else torch.float32
     r = torch.as_tensor(rho).to(device=device, dtype=td).contiguous()
     th = torch.as_tensor(theta).to(device=device, dtype=td).contiguous()
+    if th.numel() != r.numel():
+        raise ValueError("entropy_from_theta: rho and theta differ in size")
     s = torch.empty_like(r)
     _check(lib().hlbm_entropy_from_theta(F64 if dtype == "f64" else F32, float(gamma), _ptr(r),
                                          _ptr(th), _ptr(s), r.numel(), _stream()),
