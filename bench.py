@@ -278,7 +278,7 @@ def main():
                       "tile_w": params.tile_w or "auto", "tile_h": params.tile_h or "auto",
                       "status_after": int(code)},
            "roofline": roofline, "cpu_baseline": cpu, "stream_reference": stream_ref,
-           "f64": f64,
+           "f64": f64, "device": torch.cuda.get_device_name(0),
            "learned_closure": learned}
     print(json.dumps(out), flush=True)
 

@@ -211,6 +211,18 @@ def _dev_buf(t, device, nbytes, dtype=None, what="buffer"):
     return t
 
 
+def _workspace(ws, nbytes, device):
+    """A caller-given workspace (uint8 tensor of at least nbytes bytes,
+    256-byte aligned) or a new one."""
+    import torch
+    if ws is None:
+        return torch.empty(nbytes, dtype=torch.uint8, device=device)
+    _dev_buf(ws, device, nbytes, torch.uint8, "workspace")
+    if ws.data_ptr() % 256:
+        raise ValueError("workspace: must be 256-byte aligned")
+    return ws
+
+
 def _dev_field(a, p: Params, device):
     import torch
     t = torch.as_tensor(a)
@@ -239,7 +251,8 @@ class Solver:
     """One HLBM domain on the GPU.  Fields are torch tensors (or numpy arrays,
     copied to the device); either s or theta is given."""
 
-    def __init__(self, params: Params, rho, ux, uy, s=None, theta=None, device="cuda"):
+    def __init__(self, params: Params, rho, ux, uy, s=None, theta=None, device="cuda",
+                 workspace=None):
         import torch
         self.p = params
         self.device = torch.device(device)
@@ -254,7 +267,7 @@ class Solver:
         nbytes = lib().hlbm_workspace_bytes(ctypes.byref(self._cp))
         if nbytes == 0:
             raise HlbmError(HLBM_EINVAL, "hlbm_workspace_bytes")
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.workspace = _workspace(workspace, nbytes, self.device)
         h = ctypes.c_void_p()
         code = lib().hlbm_init(ctypes.byref(h), ctypes.byref(self._cp), _ptr(self.workspace),
                                nbytes, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(s), _stream())
@@ -334,7 +347,7 @@ class BatchSolver:
     non-default stream, so the solver owns one and orders it after the
     caller's current stream."""
 
-    def __init__(self, params, fields, device="cuda"):
+    def __init__(self, params, fields, device="cuda", workspace=None):
         import torch
         if len(params) != len(fields) or not params:
             raise ValueError("one field tuple per parameter set")
@@ -359,7 +372,7 @@ class BatchSolver:
         nbytes = lib().hlbm_batch_workspace_bytes(arr, len(self.params))
         if nbytes == 0:
             raise HlbmError(HLBM_EINVAL, "hlbm_batch_workspace_bytes")
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.workspace = _workspace(workspace, nbytes, self.device)
         self.stream = torch.cuda.Stream(device=self.device)  # default priority
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
         h = ctypes.c_void_p()

@@ -7,7 +7,7 @@ import ctypes
 
 import numpy as np
 
-from ._lib import HLBM_EINVAL, HlbmError, _check, _ptr, _stream, lib
+from ._lib import HLBM_EINVAL, HlbmError, _check, _ptr, _stream, _workspace, lib
 
 N_PARAMS = 11588
 
@@ -60,14 +60,14 @@ class CNN:
     addressed as x[s * sstride + c * cstride + i]; a [S][4][ny][nx] tensor
     has sstride 4 ny nx and cstride ny nx (the defaults)."""
 
-    def __init__(self, max_batch, ny, nx, params, device="cuda"):
+    def __init__(self, max_batch, ny, nx, params, device="cuda", workspace=None):
         import torch
         self.device = torch.device(device)
         self.max_batch, self.ny, self.nx = int(max_batch), int(ny), int(nx)
         nbytes = lib().hlbm_cnn_workspace_bytes(self.max_batch, self.ny, self.nx)
         if nbytes == 0:
             raise HlbmError(HLBM_EINVAL, "hlbm_cnn_workspace_bytes")
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.workspace = _workspace(workspace, nbytes, self.device)
         p = _f32(params, self.device).reshape(-1)
         if p.numel() != N_PARAMS:
             raise ValueError(f"expected {N_PARAMS} parameters")
