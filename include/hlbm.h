@@ -88,6 +88,12 @@ typedef struct {
   double wall_ux_lo;    /* bc_y = HLBM_BC_WALL: x velocity of the wall row y = 0 */
   double wall_ux_hi;    /* bc_y = HLBM_BC_WALL: x velocity of the wall row y = ny - 1 */
   double wall_theta;    /* bc_y = HLBM_BC_WALL: temperature of both walls, > 0 */
+  int32_t precise_theta; /* 0: theta = theta_ref exp(...) with fast exp and log;
+                            1: theta - theta_ref from expm1 / log1p forms accurate
+                            relative to the deviation, for slow diffusive flows
+                            where neighbouring temperatures differ by ~1e-6 of
+                            theta (FP32 thermal Couette 2 x 100: error 3e-3 ->
+                            2e-4 of the temperature rise, ~1 % slower step) */
 } hlbm_params;
 
 typedef struct hlbm_handle hlbm_handle;

@@ -38,7 +38,8 @@ class CParams(ctypes.Structure):
                 ("mu", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("rho_ref", ctypes.c_double), ("theta_ref", ctypes.c_double),
                 ("sgn_eps", ctypes.c_double), ("wall_ux_lo", ctypes.c_double),
-                ("wall_ux_hi", ctypes.c_double), ("wall_theta", ctypes.c_double)]
+                ("wall_ux_hi", ctypes.c_double), ("wall_theta", ctypes.c_double),
+                ("precise_theta", ctypes.c_int32)]
 
 
 _lib = None
@@ -153,13 +154,17 @@ class Params:
     wall_ux_lo: float = 0.0
     wall_ux_hi: float = 0.0
     wall_theta: float = 1.0
+    # theta - theta_ref computed accurately relative to the deviation (slow
+    # diffusive flows; about 1 % slower)
+    precise_theta: bool = False
 
     def c(self) -> CParams:
         return CParams(self.nx, self.ny, BC[self.bc_x], BC[self.bc_y],
                        F64 if self.dtype == "f64" else F32, PHI[self.phi_mode],
                        int(self.e1_centred), int(self.e2_off), int(self.tile_w), int(self.tile_h),
                        self.gamma, self.prandtl, self.mu, self.sigma, self.rho_ref, self.theta_ref,
-                       self.sgn_eps, self.wall_ux_lo, self.wall_ux_hi, self.wall_theta)
+                       self.sgn_eps, self.wall_ux_lo, self.wall_ux_hi, self.wall_theta,
+                       int(self.precise_theta))
 
     @property
     def torch_dtype(self):

@@ -97,7 +97,8 @@ void fill_domain(const hlbm_params *p, hlbm::HostDomain *d) {
   d->ny = p->ny;
   d->bcx = p->bc_x;
   d->bcy = p->bc_y;
-  d->flags = (p->phi_mode == HLBM_PHI_FD ? 1 : 0) | (p->e1_centred ? 2 : 0) | (p->e2_off ? 4 : 0);
+  d->flags = (p->phi_mode == HLBM_PHI_FD ? 1 : 0) | (p->e1_centred ? 2 : 0) | (p->e2_off ? 4 : 0) |
+             (p->precise_theta ? 8 : 0);
   const double g = p->gamma;
   const double cv = kCs2 / (g - 1.0), cp = g * kCs2 / (g - 1.0);
   d->mu = p->mu;
@@ -167,6 +168,7 @@ int hlbm_validate(const hlbm_params *p) {
   if (p->dtype != HLBM_F64 && p->dtype != HLBM_F32) return HLBM_EINVAL;
   if (p->phi_mode != HLBM_PHI_LBM && p->phi_mode != HLBM_PHI_FD) return HLBM_EINVAL;
   if (p->e1_centred < 0 || p->e1_centred > 1 || p->e2_off < 0 || p->e2_off > 1) return HLBM_EINVAL;
+  if (p->precise_theta < 0 || p->precise_theta > 1) return HLBM_EINVAL;
   if (p->tile_w != 0 && p->tile_w != 64 && p->tile_w != 128 && p->tile_w != 192 &&
       p->tile_w != 256)
     return HLBM_EINVAL;

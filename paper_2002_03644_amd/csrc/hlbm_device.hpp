@@ -64,6 +64,7 @@ struct StepArgs {
 };
 
 constexpr int kFlagPhiFD = 1, kFlagE1Centred = 2, kFlagE2Off = 4;
+constexpr int kFlagPreciseTheta = 8;  // theta - theta_ref from expm1 / log1p (see node_dtheta)
 constexpr int kBcWall = 2;  // rows y = 0 and y = ny - 1 are walls (ghosts beyond them clamp)
 
 // ---------------------------------------------------------------- helpers
@@ -150,6 +151,44 @@ __device__ __forceinline__ NodeMoments node_moments(const real F[kQ], const Doma
 // theta from the stored entropy (deviation form: ds = s - s_ref).
 __device__ __forceinline__ real node_theta(real rho, real sv, const DomainArgs &d) {
   return d.theta_ref * exp_r(sv * d.inv_cv + d.gm1 * (log_r(rho) - d.log_rho_ref));
+}
+
+// theta - theta_ref with relative accuracy on the deviation itself:
+// theta_ref expm1(ds / c_v + (gamma - 1) ln(rho / rho_ref)), the density ratio
+// from dr = rho - rho_ref in FP32 (log1p), rho itself in the FP64 form
+// (rho_ref = 0, theta_ref = 1 there).  The Fourier term's Laplacian is taken
+// of these deviations: in slow, well-resolved flows the temperature
+// differences between neighbours are a few 1e-6 of theta, which absolute
+// FP32 values would round to a few per cent.
+//
+// FP32 uses the hardware exp and log with the classic corrections that make
+// them accurate relative to small results: Goldberg's log1p(y) = ln(u) y /
+// (u - 1) with u = 1 + y, exact when u rounds to 1, and expm1 by its Taylor
+// series for |x| < 1/4, else Kahan's (u - 1) x / ln(u) with u = e^x.  FP64
+// uses the library functions.
+__device__ __forceinline__ float log1p_fast(float y) {
+  const float u = 1.0f + y;
+  const float um1 = u - 1.0f;
+  return um1 == 0.0f ? y : __logf(u) * div_fast(y, um1);
+}
+__device__ __forceinline__ float expm1_fast(float x) {
+  // |x| < 1/4: the Taylor series to x^7 (truncation below 1e-9 of the result)
+  if (fabsf(x) < 0.25f) {
+    const float p = 1.0f / 5040.0f;
+    return x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f +
+                x * (1.0f / 120.0f + x * (1.0f / 720.0f + x * p))))));
+  }
+  const float u = __expf(x);
+  const float um1 = u - 1.0f;
+  if (um1 == -1.0f) return -1.0f;
+  return um1 * div_fast(x, __logf(u));
+}
+__device__ __forceinline__ float node_dtheta(float dr, float rho, float sv, const DomainArgs &d) {
+  return d.theta_ref * expm1_fast(sv * d.inv_cv + d.gm1 * log1p_fast(dr / d.rho_ref));
+}
+__device__ __forceinline__ double node_dtheta(double dr, double rho, double sv,
+                                              const DomainArgs &d) {
+  return d.theta_ref * expm1(sv * d.inv_cv + d.gm1 * (log(rho) - d.log_rho_ref));
 }
 
 // van Albada limited slope b phi(a/b), phi(r) = (r^2 + r)/(r^2 + 1), zero for
@@ -288,10 +327,20 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
     const NodeMoments m = node_moments(F, d);
     const real inv_rho = rcp_fast(m.rho);
     const real ux = m.jx * inv_rho, uy = m.jy * inv_rho;
-    const real th = node_theta(m.rho, sv, d);
+    // The Fourier term's Laplacian is taken of what the theta ring holds:
+    // theta itself by default, theta - theta_ref (accurate relative to
+    // itself) with the precise-theta flag; the constant shift cancels.
+    real th, lap_val;
+    if (d.flags & kFlagPreciseTheta) {
+      lap_val = node_dtheta(m.dr, m.rho, sv, d);
+      th = d.theta_ref + lap_val;
+    } else {
+      th = node_theta(m.rho, sv, d);
+      lap_val = th;
+    }
     r_ux[j % 3][ri] = ux;
     r_uy[j % 3][ri] = uy;
-    r_th[j % 5][ri] = th;
+    r_th[j % 5][ri] = lap_val;
     r_gx[j & 1][ri] = m.rho * ux * ((real(1) - th) - ux * ux);
     r_gy[j % 3][ri] = m.rho * uy * ((real(1) - th) - uy * uy);
     r_s[j % 6][ri] = sv;
@@ -456,8 +505,9 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
                                    r_s[s0][ri + 2]);
       const real advy = muscl_term(cB_uy, r_s[sm2][ri], r_s[sm1][ri], sc, r_s[s1][ri], r_s[s2][ri]);
       const int t0 = k % 5, tn = (k + 1) % 5, ts = (k + 4) % 5;
+      // Laplacian of theta (or of theta - theta_ref, the same)
       const real lap = ((r_th[t0][ri + 1] + r_th[t0][ri - 1]) + (r_th[tn][ri] + r_th[ts][ri])) -
-                       real(4) * cB_th;
+                       real(4) * r_th[t0][ri];
       const real snew = sc - (advx + advy) + div_fast(d.lambda * lap + cB_phi, cB_rho * cB_th);
       const unsigned off = (unsigned)((y0 + k - 2) * d.nx + vx) * kEl;
 #pragma unroll

@@ -170,7 +170,8 @@ def couette_exact(eta, ma, pr, gamma):
 
 
 def thermal_couette(ny=100, nx=2, ma=0.8, pr=0.71, gamma=1.4, sigma=0.9, theta_w=300.0 / 1500.0,
-                    nu=0.1, steps=None, dtype="f64", phi_mode="lbm", device="cuda"):
+                    nu=0.1, steps=None, dtype="f64", phi_mode="lbm", precise_theta=True,
+                    device="cuda"):
     """The thermal Couette flow of Sec. 4.4 on an nx x ny channel (the paper
     uses 2 x 100, T_r = 1500 K, T_w = 300 K, sigma 0.9): periodic in x, walls
     at the rows y = 0 (at rest) and y = ny - 1 (moving at U = Ma c_w, c_w the
@@ -179,7 +180,10 @@ def thermal_couette(ny=100, nx=2, ma=0.8, pr=0.71, gamma=1.4, sigma=0.9, theta_w
     enough for the slowest thermal mode, decaying as exp(-pi^2 nu t / (Pr
     H^2)), to fall below 1e-7).  Returns the theta and u_x profiles (FP64
     numpy, averaged over x), the closed-form profiles, and the largest
-    temperature error relative to the largest temperature rise."""
+    temperature error relative to the largest temperature rise.
+    precise_theta (the default here) takes the Fourier term's Laplacian of
+    temperature deviations computed accurately, which this slow,
+    well-resolved flow needs in FP32."""
     import torch
     from ._lib import Solver
     H = ny - 1
@@ -191,7 +195,7 @@ def thermal_couette(ny=100, nx=2, ma=0.8, pr=0.71, gamma=1.4, sigma=0.9, theta_w
     ones = np.ones((ny, nx))
     p = Params(nx, ny, dtype=dtype, gamma=gamma, prandtl=pr, mu=nu, sigma=sigma, bc_y="wall",
                wall_ux_lo=0.0, wall_ux_hi=U, wall_theta=theta_w, theta_ref=theta_w,
-               phi_mode=phi_mode)
+               phi_mode=phi_mode, precise_theta=precise_theta)
     S = Solver(p, ones, U * eta[:, None] * ones, 0.0 * ones, theta=theta_w * ones, device=device)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -107,6 +107,7 @@ def test_f64_sod_4096x4():
     dict(bc_x="extrapolate", bc_y="extrapolate", phi_mode="fd", sigma=0.3),
     dict(bc_x="periodic", bc_y="extrapolate", sigma=0.9, prandtl=1.3),
     dict(e1_centred=True, e2_off=True, sigma=0.2),
+    dict(precise_theta=True, sigma=0.5),
 ])
 def test_f64_options(opts):
     nx, ny = 75, 66
