@@ -26,7 +26,7 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 size_t elem_size(int dtype) { return dtype == HLBM_F64 ? 8 : 4; }
 
 long long plane_elems(const hlbm_params *p) {
-  return (long long)round_up((size_t)p->nx * (size_t)p->ny, 64);
+  return hlbm::plane_stride(p->nx, p->ny, (int)elem_size(p->dtype));
 }
 
 struct Layout {
