@@ -246,7 +246,7 @@ FP32_TOL = {
     "vortex": dict(rho=2e-4, ux=3e-4, uy=2e-4, s=1e-7),
     "turbulence": dict(rho=3e-4, ux=2e-4, uy=2e-4, s=1e-6),
     "sod100": dict(rho=2e-5, ux=2e-5, s=2e-6),
-    "sod2000": dict(rho=5e-2, ux=2.5e-1, s=1e-2),
+    "sod2000": dict(rho=5e-4, ux=3e-3, s=1e-4),   # measured 1.2e-4, 7.3e-4, 2.1e-5
 }
 
 
