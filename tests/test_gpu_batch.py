@@ -66,6 +66,30 @@ def test_batch_bitwise_equals_single_domains(dtype, graph, tile):
     assert B.status()[0] == 0
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_with_padded_planes_equals_single_domains(dtype):
+    """A domain large enough for the padded plane stride (over 4 MiB per
+    plane) between two small ones: the batch's per-domain offsets follow the
+    padded size, and every domain still matches its single run bitwise."""
+    shapes = [(64, 64), (1100, 1031), (130, 70)]
+    params, fields = [], []
+    for k, (nx, ny) in enumerate(shapes):
+        th = hi.theta_for_cfl(0.6)
+        fields.append(hi.vortex(nx, ny, nx / 2, ny / 2, max(2.0, min(nx, ny) / 8), 0.4, 0.04,
+                                theta_inf=th, angle=0.5 * k))
+        params.append(Params(nx, ny, dtype=dtype, mu=1e-3, sigma=0.3, theta_ref=th,
+                             tile_w=192, tile_h=16))
+    B = BatchSolver(params, fields)
+    B.set_tile(192, 16)
+    B.step(6, graph=True)
+    mb = B.moments()
+    ms = singles(params, fields, 6)
+    for k in range(len(params)):
+        for key in ("rho", "ux", "uy", "s"):
+            assert torch.equal(mb[k][key], ms[k][key]), (k, key)
+    assert B.status()[0] == 0
+
+
 def test_graph_replays_match_eager_between_eager_work():
     """Replays of the captured graph, interleaved with unrelated eager work and
     synchronisations, equal an eager run after every replay."""
