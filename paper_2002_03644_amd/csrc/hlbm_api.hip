@@ -87,7 +87,7 @@ void rest_equilibrium(double rho, double theta, double f[9]) {
 }
 
 hlbm::TileShape default_tile(const hlbm_params *p) {
-  return hlbm::step_tile(p->nx, p->ny, p->tile_w, p->tile_h);
+  return hlbm::step_tile(p->nx, p->ny, p->tile_w, p->tile_h, (int)elem_size(p->dtype));
 }
 
 void fill_domain(const hlbm_params *p, hlbm::HostDomain *d) {
