@@ -29,20 +29,24 @@ struct TileShape {
 //    (row segments stay 256-byte aligned, the halo wave is a quarter of the
 //    workgroup, 16-row strips beat taller ones).  FP64 (elem_size 8), which
 //    holds two workgroups per CU, runs 2-5 % faster with 32-row strips
-//    there.  Grids narrower than 1536 columns keep 128-column tiles with
-//    32-row strips (less ragged).
+//    there.  Grids narrower than 1024 columns keep 128-column tiles with
+//    32-row strips (less ragged); from 1024 columns on, 192 x 8 measured
+//    best or tied in FP32 (1024^2 37.0-37.6 k MLUPS against 35.4-37.3 k for
+//    128 x 8, 1500^2 43.6 k against 39.1 k).
 //  - Small grids get 64-column tiles (nx <= 64) and strips halved down to 4
-//    rows until about 1024 workgroups exist (512 in FP64, whose sweep holds
-//    two workgroups per CU, so 512 fill the chip once: at 1024^2 128 x 16
-//    runs 15.8 k MLUPS against 13.4 k for 128 x 8): a strip is swept
-//    serially, so a few tall strips would leave the chip idle.
+//    rows until about 768 workgroups exist in FP32 (half a round of six per
+//    CU; at 1024^2 192 x 8, 768 workgroups, edges out 192 x 4) and 512 in
+//    FP64, whose sweep holds two workgroups per CU, so 512 fill the chip
+//    once (at 1024^2 128 x 16 runs 15.8 k MLUPS against 13.4 k for
+//    128 x 8): a strip is swept serially, so a few tall strips would leave
+//    the chip idle.
 inline TileShape step_tile(int nx, int ny, int tile_w, int tile_h, int elem_size) {
   TileShape t;
-  t.bw = tile_w ? tile_w : (nx <= 64 ? 64 : (nx >= 1536 ? 192 : 128));
+  t.bw = tile_w ? tile_w : (nx <= 64 ? 64 : (nx >= 1024 ? 192 : 128));
   int rows = tile_h ? tile_h : (t.bw == 192 && elem_size == 4 ? 16 : 32);
   if (!tile_h) {
     const long long nbx = (nx + t.bw - 1) / t.bw;
-    const long long want = elem_size == 8 ? 512 : 1024;
+    const long long want = elem_size == 8 ? 512 : 768;
     while (rows > 4 && nbx * ((ny + rows - 1) / rows) < want) rows /= 2;
   }
   if (rows > ny) rows = ny;
