@@ -368,8 +368,10 @@ struct hlbm_batch {
   size_t state_bytes = 0;             // one buffer
   int max_items = 0, nitems = 0, tile_w = 128, tile_h = 32, grid = 1, cur = 0, ncu = 1;
   int64_t steps = 0, nodes = 0;
-  hipGraphExec_t graph = nullptr;
-  int graph_cur = -1;
+  // captured plain steps: graph[0] one ping-pong pair, graph[1] kLongPairs
+  // pairs (fewer replays, so fewer gaps between them, for short steps)
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  int graph_cur[2] = {-1, -1};
   hipGraphExec_t cgraph = nullptr;    // captured corrected steps (hlbm_closure_step)
   int cgraph_cur = -1, cgraph_conserve = -1, cgraph_version = -1, cgraph_every = -1;
   const hlbm_cnn *cgraph_net = nullptr;
@@ -460,14 +462,54 @@ hipError_t batch_upload_items(hlbm_batch *b, int tw, int th, hipStream_t st) {
   const int per_cu = b->dtype == HLBM_F64 ? hlbm::f64::batch_blocks_per_cu(tw)
                                           : hlbm::f32::batch_blocks_per_cu(tw);
   b->grid = std::max(1, std::min(b->nitems, per_cu * b->ncu));
-  if (b->graph) {
-    (void)hipGraphExecDestroy(b->graph);
-    b->graph = nullptr;
+  for (hipGraphExec_t &g : b->graph) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
   }
   if (b->cgraph) {
     (void)hipGraphExecDestroy(b->cgraph);
     b->cgraph = nullptr;
   }
+  return hipSuccess;
+}
+
+hipError_t batch_launch(hlbm_batch *b, int from, hipStream_t st);
+
+// Ping-pong step pairs per long graph.  Replaying a two-step graph leaves a
+// gap of a few microseconds between replays, which for small batches (8 x
+// 256^2: 23 us per step) costs about 8 %; sixteen steps per replay recover
+// it (21.2 us).
+constexpr int kLongPairs = 8;
+
+// Graph `which` of `pairs` ping-pong pairs from the current buffer (an even
+// number of steps leaves the state there), captured on first use and again
+// after the current buffer changed; the tile shape's changes destroy it.
+hipError_t batch_graph(hlbm_batch *b, int which, int pairs, hipStream_t st) {
+  if (b->graph[which] && b->graph_cur[which] == b->cur) return hipSuccess;
+  if (b->graph[which]) {
+    (void)hipGraphExecDestroy(b->graph[which]);
+    b->graph[which] = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t el = hipSuccess;
+  for (int k = 0; k < pairs && el == hipSuccess; ++k) {
+    el = batch_launch(b, b->cur, st);
+    if (el == hipSuccess) el = batch_launch(b, b->cur ^ 1, st);
+  }
+  e = hipStreamEndCapture(st, &g);
+  if (el != hipSuccess || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return el != hipSuccess ? el : e;
+  }
+  e = hipGraphInstantiate(&b->graph[which], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->graph[which] = nullptr;
+    return e;
+  }
+  b->graph_cur[which] = b->cur;
   return hipSuccess;
 }
 
@@ -570,33 +612,17 @@ int hlbm_batch_step(hlbm_batch *b, int32_t nsteps, int32_t use_graph, hlbm_strea
   hipStream_t st = (hipStream_t)stream;
   if (use_graph && !st) return HLBM_EINVAL;  // the legacy null stream cannot be captured
   int n = nsteps;
-  if (use_graph && n >= 2) {
-    if (!b->graph || b->graph_cur != b->cur) {
-      if (b->graph) {
-        (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
+  if (use_graph) {
+    // long graphs while at least kLongPairs pairs remain, then single pairs;
+    // an odd last step runs eagerly
+    for (int which = 1; which >= 0; --which) {
+      const int len = 2 * (which ? kLongPairs : 1);
+      if (n < len) continue;
+      if (batch_graph(b, which, len / 2, st) != hipSuccess) return HLBM_EHIP;
+      for (; n >= len; n -= len) {
+        if (hipGraphLaunch(b->graph[which], st) != hipSuccess) return HLBM_EHIP;
+        b->steps += len;
       }
-      hipGraph_t g = nullptr;
-      hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-      if (e != hipSuccess) return HLBM_EHIP;
-      hipError_t e1 = batch_launch(b, b->cur, st);
-      hipError_t e2 = batch_launch(b, b->cur ^ 1, st);
-      e = hipStreamEndCapture(st, &g);
-      if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return HLBM_EHIP;
-      }
-      e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (e != hipSuccess) {
-        b->graph = nullptr;
-        return HLBM_EHIP;
-      }
-      b->graph_cur = b->cur;
-    }
-    for (; n >= 2; n -= 2) {
-      if (hipGraphLaunch(b->graph, st) != hipSuccess) return HLBM_EHIP;
-      b->steps += 2;
     }
   }
   for (; n > 0; --n) {
@@ -717,7 +743,8 @@ int64_t hlbm_batch_steps_done(const hlbm_batch *b) { return b ? b->steps : -1; }
 
 void hlbm_batch_destroy(hlbm_batch *b) {
   if (!b) return;
-  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  for (hipGraphExec_t g : b->graph)
+    if (g) (void)hipGraphExecDestroy(g);
   if (b->cgraph) (void)hipGraphExecDestroy(b->cgraph);
   delete b;
 }

@@ -91,15 +91,18 @@ def test_batch_with_padded_planes_equals_single_domains(dtype):
 
 
 def test_graph_replays_match_eager_between_eager_work():
-    """Replays of the captured graph, interleaved with unrelated eager work and
-    synchronisations, equal an eager run after every replay."""
+    """Replays of the captured graphs (two-step and sixteen-step, and an odd
+    count that ends eagerly and moves the state to the other buffer, so the
+    graphs are captured again), interleaved with unrelated eager work and
+    synchronisations, equal an eager run after every call."""
     params, fields = domain_set("f32")
     A = BatchSolver(params, fields)
     E = BatchSolver(params, fields)
     x = torch.randn(512, 512, device="cuda")
-    for rep in range(5):
-        A.step(6, graph=True)
-        E.step(6, graph=False)
+    counts = (6, 22, 6, 35, 16, 6)
+    for rep, n in enumerate(counts):
+        A.step(n, graph=True)
+        E.step(n, graph=False)
         y = (x @ x).sum()          # eager work between replays
         torch.cuda.synchronize()
         assert torch.isfinite(y)
@@ -107,7 +110,7 @@ def test_graph_replays_match_eager_between_eager_work():
         for k in range(len(params)):
             assert torch.equal(ma[k]["rho"], me[k]["rho"]), (rep, k)
             assert torch.equal(ma[k]["s"], me[k]["s"]), (rep, k)
-    assert A.steps == E.steps == 30
+    assert A.steps == E.steps == sum(counts)
 
 
 def test_diverged_domain_is_isolated():
