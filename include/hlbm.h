@@ -206,8 +206,11 @@ int hlbm_batch_init(hlbm_batch **out, const hlbm_params *params, int32_t count, 
                     size_t ws_bytes, const void *rho, const void *ux, const void *uy,
                     const void *s, hlbm_stream_t stream);
 
-/* Enqueue nsteps steps of all domains.  use_graph = 1 captures a two-step
- * hipGraph on first use (stream must not be NULL) and replays it. */
+/* Enqueue nsteps steps of all domains.  use_graph = 1 (stream must not be
+ * NULL) replays a captured sixteen-step hipGraph while sixteen or more steps
+ * remain, then a two-step one, and runs an odd last step eagerly; each graph
+ * is captured on first use and again after the state has moved to the other
+ * buffer or the tile shape changed.  HLBM_EHIP if a capture or launch fails. */
 int hlbm_batch_step(hlbm_batch *b, int32_t nsteps, int32_t use_graph, hlbm_stream_t stream);
 
 /* Concatenated macroscopic fields of all domains (NULL outputs skipped). */
