@@ -67,7 +67,7 @@ def f64_same_config(n, fields, tile_w, tile_h, steps=100):
     `steps` steps after 5 warm-up steps, for context beside the FP32 line."""
     import torch
 
-    from paper_2002_03644_amd import Params, Solver
+    from paper_2002_03644_amd import Params, Solver, launch_shape
     r, u, v, t = fields
     S = Solver(Params(n, n, dtype="f64", mu=1e-3, sigma=0.0, tile_w=tile_w, tile_h=tile_h),
                r, u, v, theta=t)
@@ -84,9 +84,10 @@ def f64_same_config(n, fields, tile_w, tile_h, steps=100):
     del S
     torch.cuda.empty_cache()
     gbs = 2 * BYTES_PER_NODE * n * n / (ms / 1e3) / 1e9
+    tw, th = launch_shape(Params(n, n, dtype="f64", tile_w=tile_w, tile_h=tile_h))
     return {"mlups": round(n * n / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 4),
             "achieved": round(gbs, 1), "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-            "steps": steps, "status_after": int(code)}
+            "steps": steps, "status_after": int(code), "tile_w": tw, "tile_h": th}
 
 
 def gpu_same_window(oracle_mlups, n=1024, steps=150):
@@ -205,7 +206,7 @@ def main():
     import torch
 
     import hlbm_inputs as hi
-    from paper_2002_03644_amd import Params, Solver
+    from paper_2002_03644_amd import Params, Solver, launch_shape
 
     n = args.n
     print(f"[bench] generating {n}x{n} turbulence", file=sys.stderr, flush=True)
@@ -275,7 +276,8 @@ def main():
            "config": {"workload": f"decaying compressible turbulence {n}x{n} periodic, "
                                   "Ma_t 0.5, nu 1e-3, sigma 0, FP32 storage",
                       "nx": n, "ny": n, "global_batch": 1, "parallelism": "none",
-                      "tile_w": params.tile_w or "auto", "tile_h": params.tile_h or "auto",
+                      "tile_w": launch_shape(params)[0], "tile_h": launch_shape(params)[1],
+                      "tiles_given": bool(params.tile_w and params.tile_h),
                       "status_after": int(code)},
            "roofline": roofline, "cpu_baseline": cpu, "stream_reference": stream_ref,
            "f64": f64, "device": torch.cuda.get_device_name(0),

@@ -113,6 +113,15 @@ size_t hlbm_state_bytes(const hlbm_params *p);
 /* Check parameters without touching the GPU: HLBM_OK or HLBM_EINVAL. */
 int hlbm_validate(const hlbm_params *p);
 
+/* Tile shape hlbm_step launches for these parameters: tile_w / tile_h as
+ * given, or the defaults when they are 0 (192-column tiles from 1024 columns,
+ * 128 below, 64 for nx <= 64; 16-row strips at 192 columns in FP32, 32
+ * otherwise, halved down to 4 rows until about 768 workgroups exist in FP32
+ * or 512 in FP64; never more rows than ny).  Writes *host_tile_w and
+ * *host_tile_h; HLBM_OK, or HLBM_EINVAL if the parameters are invalid or a
+ * pointer is NULL.  Host-only; callable without a GPU. */
+int hlbm_launch_shape(const hlbm_params *p, int32_t *host_tile_w, int32_t *host_tile_h);
+
 /* Initialise a domain from macroscopic fields (algorithm of Sec. 3.5, steps
  * 1-4): F0 = f^eq + f^1[a1FD] - psi/2 at every node, so the first step sees
  * the finite-difference off-equilibrium stress for any sigma.

@@ -59,6 +59,7 @@ def lib():
         sig = {
             "hlbm_workspace_bytes": (sz, [PP]),
             "hlbm_state_bytes": (sz, [PP]),
+            "hlbm_launch_shape": (ctypes.c_int, [PP, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
             "hlbm_validate": (ctypes.c_int, [PP]),
             "hlbm_init": (ctypes.c_int, [ctypes.POINTER(vp), PP, vp, sz, vp, vp, vp, vp, vp]),
             "hlbm_step": (ctypes.c_int, [vp, i32, vp]),
@@ -180,6 +181,15 @@ def validate(p: Params) -> int:
 def workspace_bytes(p: Params) -> int:
     cp = p.c()
     return int(lib().hlbm_workspace_bytes(ctypes.byref(cp)))
+
+
+def launch_shape(p: Params):
+    """(tile_w, tile_h) that the single-domain step launches for p."""
+    cp = p.c()
+    w, h = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().hlbm_launch_shape(ctypes.byref(cp), ctypes.byref(w), ctypes.byref(h)),
+           "hlbm_launch_shape")
+    return int(w.value), int(h.value)
 
 
 def _stream(stream=None):

@@ -183,6 +183,14 @@ int hlbm_validate(const hlbm_params *p) {
   return HLBM_OK;
 }
 
+int hlbm_launch_shape(const hlbm_params *p, int32_t *host_tile_w, int32_t *host_tile_h) {
+  if (!host_tile_w || !host_tile_h || hlbm_validate(p) != HLBM_OK) return HLBM_EINVAL;
+  const hlbm::TileShape t = default_tile(p);
+  *host_tile_w = t.bw;
+  *host_tile_h = t.rows;
+  return HLBM_OK;
+}
+
 size_t hlbm_workspace_bytes(const hlbm_params *p) {
   if (hlbm_validate(p) != HLBM_OK) return 0;
   return layout_of(p).total;

@@ -107,6 +107,39 @@ def test_large_planes_get_a_stride_off_the_power_of_two(dt, es):
             assert base < plane <= base + 192 * 1024 + 256, (nx, ny)
 
 
+@pytest.mark.parametrize("nx,ny,dt,shape", [
+    (8192, 8192, "f32", (192, 16)),   # the bench grid
+    (8192, 8192, "f64", (192, 32)),
+    (15446, 15446, "f32", (192, 16)),
+    (1500, 1500, "f32", (192, 8)),    # halved until about 768 workgroups
+    (1024, 1024, "f32", (192, 8)),
+    (1024, 1024, "f64", (192, 8)),    # about 512 in FP64
+    (1023, 1023, "f32", (128, 8)),
+    (768, 768, "f32", (128, 4)),
+    (64, 64, "f32", (64, 4)),
+    (2, 100, "f64", (64, 4)),         # the Couette channel
+    (1, 1, "f64", (64, 1)),           # never more rows than ny
+    (300, 3, "f32", (128, 3)),
+])
+def test_default_launch_shape(nx, ny, dt, shape):
+    from paper_2002_03644_amd import launch_shape
+    assert launch_shape(_params(nx=nx, ny=ny, dtype=dt)) == shape
+
+
+def test_launch_shape_takes_given_tiles_and_rejects_bad_input():
+    import ctypes as C
+
+    from paper_2002_03644_amd import launch_shape
+    from paper_2002_03644_amd._lib import lib
+    assert launch_shape(_params(nx=100, ny=100, tile_w=256, tile_h=7)) == (256, 7)
+    assert launch_shape(_params(nx=100, ny=5, tile_w=64, tile_h=40)) == (64, 5)
+    w = C.c_int32()
+    p = _params(nx=100, ny=100).c()
+    assert lib().hlbm_launch_shape(C.byref(p), C.byref(w), None) != 0
+    bad = _params(nx=100, ny=100, tile_w=100).c()
+    assert lib().hlbm_launch_shape(C.byref(bad), C.byref(w), C.byref(w)) != 0
+
+
 def test_largest_grid_accepted():
     from paper_2002_03644_amd import HLBM_OK, validate
     assert validate(_params(nx=15446, ny=15446)) == HLBM_OK  # 9 n^2 < 2^31
