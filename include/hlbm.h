@@ -74,7 +74,8 @@ typedef struct {
                            1: without it (original-model ablation) */
   int32_t tile_w;       /* tile width in columns (64, 128, 192 or 256; the workgroup has
                            tile_w + 64 lanes, the extra wave holds the halo), 0 = auto */
-  int32_t tile_h;       /* output rows per workgroup strip (>= 1), 0 = auto */
+  int32_t tile_h;       /* output rows per workgroup strip (>= 1), 0 = auto;
+                           hlbm_launch_shape reports what a step will use */
   double gamma;         /* heat-capacity ratio, > 1 */
   double prandtl;       /* Prandtl number, > 0; lambda = mu c_p / Pr */
   double mu;            /* dynamic viscosity, >= 0; local tau = mu / p */
