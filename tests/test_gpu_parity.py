@@ -261,6 +261,8 @@ FP32_TOL = {
     "turbulence": dict(rho=3e-4, ux=2e-4, uy=2e-4, s=1e-6),
     "sod100": dict(rho=2.5e-6, ux=6e-5, s=8e-7),   # measured 6.4e-7, 1.5e-5, 2.1e-7
     "sod2000": dict(rho=5e-4, ux=3e-3, s=1e-4),   # measured 1.2e-4, 7.3e-4, 2.1e-5
+    "mach2_300": dict(rho=6e-5, ux=1e-4, s=3e-7),     # measured 1.4e-5, 2.5e-5, 6.7e-8
+    "mach2_2000": dict(rho=3.5e-3, ux=7e-3, s=1.4e-5),  # measured 8.6e-4, 1.7e-3, 3.3e-6
 }
 
 
@@ -295,6 +297,21 @@ def test_f32_turbulence_tolerance():
     ma, mb, _, B = f32_vs_f64(n, n, f, 1000, mu=1e-3, sigma=0.0)
     assert B.status()[0] == HLBM_OK
     check_tol("turbulence", ma, mb, FIELDS)
+
+
+def test_f32_mach2_shock_tolerance():
+    """Mach-2 normal shock 2048 x 512 from Rankine-Hugoniot states (x
+    extrapolated, seeded upstream perturbation, theta_ref at the upstream
+    temperature): FP32 against FP64 after 300 and 2000 steps."""
+    nx, ny = 2048, 512
+    f = hi.normal_shock(nx, ny, mach=2.0, theta1=0.1, perturb=1e-3, seed=0)
+    ma, mb, A, B = f32_vs_f64(nx, ny, f, 300, theta_ref=0.1, mu=1e-3, sigma=0.0,
+                              phi_mode="fd", bc_x="extrapolate")
+    check_tol("mach2_300", ma, mb, ("rho", "ux", "s"))
+    A.step(1700)
+    B.step(1700)
+    assert A.status()[0] == HLBM_OK and B.status()[0] == HLBM_OK
+    check_tol("mach2_2000", gpu_moments(A), gpu_moments(B), ("rho", "ux", "s"))
 
 
 def test_f32_sod_tolerance():
