@@ -528,6 +528,8 @@ def bench_batch(args):
            "config": {"workload": "256 periodic domains 64^2..1016^2 (seed 0), vortex or "
                                   "turbulence, Mach 0.1-2.0, FP32, hipGraph replay",
                       "nodes_total": B.nodes, "nodes_active_at_end": active,
+                      # all domains over the timed steps, frozen ones included
+                      "all_nodes_mlups": round(B.nodes * args.steps / (ms / 1e3) / 1e6, 1),
                       "domains_diverged": int(bad), "tile_w": tw, "tile_h": th},
            "roofline": {"bound": "hbm",
                         "achieved": round(BYTES_PER_NODE * active / (ms / args.steps / 1e3) / 1e9,
