@@ -191,7 +191,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "path is a design note, not part of this build", file=sys.stderr)
+              "sharding is described in the design notes but not implemented", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch256":
         return bench_batch(args)
@@ -347,7 +347,7 @@ def learned_closure():
                         f"fine {nf}^2 (mu {setup.mu_fine}) restricted {setup.factor}x to {nc}^2; "
                         f"train seeds {len(setup.train_seeds)}, eval seeds "
                         f"{len(setup.eval_seeds)} batched, {setup.coarse_steps} coarse steps, "
-                        "error = ||rho - rho_judge|| / ||rho_judge - mean|| over checkpoints "
+                        "error = ||rho - rho_fine|| / ||rho_fine - mean|| over checkpoints "
                         f"{list(setup.checkpoints)}, times hipGraph-replayed"}
 
 

@@ -6,7 +6,7 @@
  * small convolutional network that predicts, from the coarse moments
  * X = (rho, u_x, u_y, theta), the increment that brings them towards the
  * restriction of a fine-grid HLBM run of the same flow.  The fine run is both
- * the source of the training targets and the judge of the error.
+ * the source of the training targets and the reference for the error.
  *
  * Network: three 3x3 convolutions 4 -> 32 -> 32 -> 4 with periodic padding
  * and ReLU after the first two (11 588 parameters), on per-channel

@@ -17,8 +17,8 @@ Setup (the method's own data; the paper has no learned component):
   per-channel standardised;
 * inference: after every `every` coarse steps X <- X + CNN(X) with the mass
   and momentum of each domain kept (hlbm_closure_step);
-* judge: the fine run restricted to the coarse grid; density error
-  e = ||rho - rho_judge||_2 / ||rho_judge - <rho_judge>||_2 averaged over the
+* reference: the fine run restricted to the coarse grid; density error
+  e = ||rho - rho_fine||_2 / ||rho_fine - <rho_fine>||_2 averaged over the
   held-out seeds and the checkpoints;
 * plain ladder: plain runs at intermediate resolutions N (initialised from
   the Fourier-truncated fine initial field, mu = mu_fine N / fine_n,
@@ -203,10 +203,10 @@ def fourier_resample(a, n):
     return np.fft.irfft2(G, s=(n, n)) * (n * n) / (N * N)
 
 
-def density_error(rho, judge):
-    """||rho - judge||_2 / ||judge - <judge>||_2 per sample."""
-    d = (rho.double() - judge.double()).flatten(1)
-    j = judge.double().flatten(1)
+def density_error(rho, fine_ref):
+    """||rho - fine_ref||_2 / ||fine_ref - <fine_ref>||_2 per sample."""
+    d = (rho.double() - fine_ref.double()).flatten(1)
+    j = fine_ref.double().flatten(1)
     j = j - j.mean(dim=1, keepdim=True)
     return (d.norm(dim=1) / j.norm(dim=1)).cpu().numpy()
 
@@ -307,7 +307,7 @@ def fit(setup: ClosureSetup, steps=20000, batch=32, lr=2e-3, clip=4.0, seed=0, l
     return net, rec
 
 
-def _arm(make, advance, targets, n_res, nc, judge, nseeds):
+def _arm(make, advance, targets, n_res, nc, fine_ref, nseeds):
     """Run one arm to each checkpoint's step count; density errors [cp][seed]."""
     B = make()
     errs, done = [], 0
@@ -318,7 +318,7 @@ def _arm(make, advance, targets, n_res, nc, judge, nseeds):
         rho = m["rho"].view(nseeds, n_res, n_res)
         if n_res != nc:
             rho, _, _ = to_coarse(rho, m["ux"].view_as(rho), m["uy"].view_as(rho), nc)
-        errs.append(density_error(rho, judge[:, cp, 0]))
+        errs.append(density_error(rho, fine_ref[:, cp, 0]))
     bad = int(B.status()[0])
     del B
     return np.array(errs), bad
@@ -333,7 +333,7 @@ def _ladder_fields(seeds, N, setup, fine0):
     return out
 
 
-def evaluate(net: CNN, setup: ClosureSetup, seeds=None, ladder=None, judge=None, timing=True,
+def evaluate(net: CNN, setup: ClosureSetup, seeds=None, ladder=None, fine_ref=None, timing=True,
              device="cuda"):
     """Learned and plain coarse runs of the held-out seeds against the
     restricted fine runs (see the module docstring).  Timings are for
@@ -347,10 +347,10 @@ def evaluate(net: CNN, setup: ClosureSetup, seeds=None, ladder=None, judge=None,
         for cp in cps + [steps]:
             if (cp * N) % nc:
                 raise ValueError(f"checkpoint {cp} is not a whole number of steps at {N}")
-    if judge is None:
-        judge, _ = restricted_trajectories(seeds, setup, steps=steps, device=device)
+    if fine_ref is None:
+        fine_ref, _ = restricted_trajectories(seeds, setup, steps=steps, device=device)
     thetas = [seed_flow(s, setup)[1] for s in seeds]
-    x0 = judge[:, 0]
+    x0 = fine_ref[:, 0]
     cparams = [_params(nc, setup.mu_coarse, th, setup) for th in thetas]
     cfields = [(x0[j, 0], x0[j, 1], x0[j, 2], x0[j, 3]) for j in range(len(seeds))]
     make_c = lambda: BatchSolver(cparams, cfields, device=device)  # noqa: E731
@@ -367,15 +367,15 @@ def evaluate(net: CNN, setup: ClosureSetup, seeds=None, ladder=None, judge=None,
     plain = lambda B, n: B.step(n, graph=True)  # noqa: E731
     ns = len(seeds)
     diverged = {}
-    el, diverged["learned"] = _arm(make_c, learned, [(c, c) for c in cps], nc, nc, judge, ns)
-    ep, diverged[nc] = _arm(make_c, plain, [(c, c) for c in cps], nc, nc, judge, ns)
+    el, diverged["learned"] = _arm(make_c, learned, [(c, c) for c in cps], nc, nc, fine_ref, ns)
+    ep, diverged[nc] = _arm(make_c, plain, [(c, c) for c in cps], nc, nc, fine_ref, ns)
     e_plain, curves = {nc: float(ep.mean()), nf: 0.0}, {nc: ep.mean(axis=1).tolist()}
     fine0 = {s: fine_initial(s, setup) for s in seeds}
     for N in ladder:
         pm = [_params(N, setup.mu_fine * N / nf, th, setup) for th in thetas]
         fl = _ladder_fields(seeds, N, setup, fine0)
         make = lambda pm=pm, fl=fl: BatchSolver(pm, fl, device=device)  # noqa: E731
-        e, diverged[N] = _arm(make, plain, [(c, c * N // nc) for c in cps], N, nc, judge, ns)
+        e, diverged[N] = _arm(make, plain, [(c, c * N // nc) for c in cps], N, nc, fine_ref, ns)
         e_plain[N] = float(e.mean())
         curves[N] = e.mean(axis=1).tolist()
 

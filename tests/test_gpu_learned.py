@@ -4,7 +4,7 @@ Reduced protocol (same recipe as the full one, fewer seeds and steps): 32
 training seeds of 1024^2 decaying turbulence (Ma_t 0.25-0.45) restricted 4x
 to 256^2, 100 coarse steps each, one correction per 10 coarse steps; the
 network trained on the GPU by the library's kernels; two held-out seeds
-judged against their restricted fine runs.  The corrected 256^2 runs must have a lower density error than the
+measured against their restricted fine runs.  The corrected 256^2 runs must have a lower density error than the
 plain 256^2 runs, at every checkpoint, and stay finite."""
 import numpy as np
 import pytest
