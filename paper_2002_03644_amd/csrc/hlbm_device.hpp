@@ -243,17 +243,19 @@ __device__ __forceinline__ real muscl_term(real u, real sm2, real sm1, real s0, 
 //
 // Ring depths are the smallest the two barriers per iteration allow (only a
 // write of A(i+1) may overlap a read of C(i-2) of another wave):
-//   u_x, u_y, Gamma_y: 3 rows (B reads rows k-1..k+1);  Gamma_x: 2 (row k);
+//   u_x, u_y, Gamma_x: 2 rows (B reads the x-neighbours of row k; rows k-1
+//   and k+1 of its own column, and Gamma_y entirely, come from registers);
 //   theta: 5 (C reads rows k-1 and k+1);  s: 6 (C reads rows k-2..k+2);
 //   post-collision populations by the row they stream from: c_y = 0 -> 2,
 //   c_y = +1 (read one row later) -> 3, c_y = -1 (read in the same row) -> 1;
 //   in registers the same delays: population 0 one row, 2 two rows, 4 none.
-// 34 rows of CW + 4 floats in all: 26.7 KB at CW = 192, six workgroups per CU.
+// 29 rows of CW + 4 floats in all: 22.7 KB at CW = 192, seven workgroups per
+// CU.
 // Shared memory of one tile sweep.
 template <int CW>
 struct TileRings {
   static constexpr int W = CW + 4;  // ring width: tile plus halo
-  real ux[3][W], uy[3][W], gy[3][W], gx[2][W];
+  real ux[2][W], uy[2][W], gx[2][W];
   real th[5][W], s[6][W];
   // post-collision populations that stream across columns; 0, 2 and 4
   // (c_x = 0) stay in their lane's registers
@@ -279,7 +281,6 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
   }
   auto &r_ux = R.ux;
   auto &r_uy = R.uy;
-  auto &r_gy = R.gy;
   auto &r_gx = R.gx;
   auto &r_th = R.th;
   auto &r_s = R.s;
@@ -310,6 +311,9 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
   // Node state of rows k (s0_*) and k+1 (s1_*) carried from A to B.
   real s0_dr = 0, s0_rho = 1, s0_pxx = 0, s0_pyy = 0, s0_pxy = 0, s0_ux = 0, s0_uy = 0, s0_th = 1;
   real s1_dr = 0, s1_rho = 1, s1_pxx = 0, s1_pyy = 0, s1_pxy = 0, s1_ux = 0, s1_uy = 0, s1_th = 1;
+  // B's stencil along y within the lane's own column, in registers: u of row
+  // k-1 and Gamma_y = rho u_y (1 - theta - u_y^2) of rows k-1, k, k+1
+  real m_ux = 0, m_uy = 0, m_gy = 0, c_gy = 0, n_gy = 0;
   // B -> C carry: B(k) fills nB_*, copied to cB_* at the end of the
   // iteration, read by C(k) in the next one.
   real nB_ux = 0, nB_uy = 0, nB_rho = 1, nB_th = 1, nB_phi = 0;
@@ -338,12 +342,16 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
       th = node_theta(m.rho, sv, d);
       lap_val = th;
     }
-    r_ux[j % 3][ri] = ux;
-    r_uy[j % 3][ri] = uy;
+    r_ux[j & 1][ri] = ux;
+    r_uy[j & 1][ri] = uy;
     r_th[j % 5][ri] = lap_val;
     r_gx[j & 1][ri] = m.rho * ux * ((real(1) - th) - ux * ux);
-    r_gy[j % 3][ri] = m.rho * uy * ((real(1) - th) - uy * uy);
     r_s[j % 6][ri] = sv;
+    m_ux = s0_ux;
+    m_uy = s0_uy;
+    m_gy = c_gy;
+    c_gy = n_gy;
+    n_gy = m.rho * uy * ((real(1) - th) - uy * uy);
     s0_dr = s1_dr;
     s0_rho = s1_rho;
     s0_pxx = s1_pxx;
@@ -386,13 +394,14 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
     // ---------------- B(k), k = i-1: collision
     if (i >= 2) {
       const int k = i - 1;
-      const int sc = k % 3, sn = (k + 1) % 3, ss = (k + 2) % 3;
+      const int sc = k % 3;
       if (b_col) {
         const real rho = s0_rho, ux = s0_ux, uy = s0_uy, th = s0_th;
-        const real uxe = r_ux[sc][ri + 1], uxw = r_ux[sc][ri - 1];
-        const real uye = r_uy[sc][ri + 1], uyw = r_uy[sc][ri - 1];
-        const real uxn = r_ux[sn][ri], uxs = r_ux[ss][ri];
-        const real uyn = r_uy[sn][ri], uys = r_uy[ss][ri];
+        const int su = k & 1;
+        const real uxe = r_ux[su][ri + 1], uxw = r_ux[su][ri - 1];
+        const real uye = r_uy[su][ri + 1], uyw = r_uy[su][ri - 1];
+        const real uxn = s1_ux, uxs = m_ux;
+        const real uyn = s1_uy, uys = m_uy;
         const real dxux = real(0.5) * (uxe - uxw), dxuy = real(0.5) * (uye - uyw);
         const real dyux = real(0.5) * (uxn - uxs), dyuy = real(0.5) * (uyn - uys);
         const real div = dxux + dyuy;
@@ -405,8 +414,8 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
         // E1 (upwind in the sign of the node velocity; centred inside the band)
         const real gc = r_gx[k & 1][ri];
         const real gxe = r_gx[k & 1][ri + 1], gxw = r_gx[k & 1][ri - 1];
-        const real gcy = r_gy[sc][ri];
-        const real gyn = r_gy[sn][ri], gys = r_gy[ss][ri];
+        const real gcy = c_gy;
+        const real gyn = n_gy, gys = m_gy;
         real e1x, e1y;
         if (d.flags & kFlagE1Centred) {
           e1x = real(0.5) * (gxe - gxw);
