@@ -67,6 +67,34 @@ def test_batch_bitwise_equals_single_domains(dtype, graph, tile):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_with_mixed_options_equals_single_domains(dtype):
+    """Every per-domain option travels in the batch's parameter table: domains
+    with precise theta, the original-model ablation (centred E1, no E2),
+    Phi by finite differences, extrapolated x boundaries and their own
+    gamma and Prandtl number each match their single run bitwise."""
+    opts = [dict(precise_theta=True), dict(e1_centred=True, e2_off=True),
+            dict(phi_mode="fd", bc_x="extrapolate"), dict(gamma=5.0 / 3.0, prandtl=2.0),
+            dict()]
+    params, fields = [], []
+    for k, o in enumerate(opts):
+        nx, ny = 96 + 17 * k, 70 + 9 * k
+        th = hi.theta_for_cfl(0.5)
+        fields.append(hi.vortex(nx, ny, nx / 2, ny / 2, 7, 0.4, 0.04, theta_inf=th,
+                                gamma=o.get("gamma", 1.4), angle=0.4 * k))
+        params.append(Params(nx, ny, dtype=dtype, mu=1e-3, sigma=0.25, theta_ref=th,
+                             tile_w=128, tile_h=16, **o))
+    B = BatchSolver(params, fields)
+    B.set_tile(128, 16)
+    B.step(19, graph=True)
+    mb = B.moments()
+    ms = singles(params, fields, 19)
+    for k in range(len(params)):
+        for key in ("rho", "ux", "uy", "s"):
+            assert torch.equal(mb[k][key], ms[k][key]), (k, key)
+    assert B.status()[0] == 0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_batch_with_padded_planes_equals_single_domains(dtype):
     """A domain large enough for the padded plane stride (over 4 MiB per
     plane) between two small ones: the batch's per-domain offsets follow the
