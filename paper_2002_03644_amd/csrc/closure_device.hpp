@@ -116,10 +116,11 @@ __global__ __launch_bounds__(kCorrThreads) void k_corr_apply(CorrArgs a) {
     real df[kQ];
     project(e2.A0 - e1.A0, e2.Ax - e1.Ax, e2.Ay - e1.Ay, e2.Axx - e1.Axx, e2.Axy - e1.Axy,
             e2.Ayy - e1.Ayy, e2.Axxy - e1.Axxy, e2.Axyy - e1.Axyy, e2.Axxyy - e1.Axxyy, df);
+    const long long o = state_off(d, i);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) st[q * P + i] += df[q];
+    for (int q = 0; q < kQ; ++q) st[q * P + o] += df[q];
     const real cv = real(1) / d.inv_cv;
-    st[9 * P + i] += cv * (log_r(th2 / th) - d.gm1 * log_r(r2 / r));
+    st[9 * P + o] += cv * (log_r(th2 / th) - d.gm1 * log_r(r2 / r));
   }
 }
 
@@ -140,10 +141,11 @@ __global__ __launch_bounds__(256) void k_batch_moments(BatchFieldArgs a) {
   const long long fo = a.foffs[k];
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
+    const long long o = state_off(d, i);
     real F[kQ];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) F[q] = st[q * P + i];
-    const real sv = st[9 * P + i];
+    for (int q = 0; q < kQ; ++q) F[q] = st[q * P + o];
+    const real sv = st[9 * P + o];
     const NodeMoments m = node_moments(F, d);
     if (a.rho) a.rho[fo + i] = m.rho;
     if (a.ux) a.ux[fo + i] = m.jx / m.rho;

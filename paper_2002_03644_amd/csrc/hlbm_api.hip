@@ -94,6 +94,7 @@ void fill_domain(const hlbm_params *p, hlbm::HostDomain *d) {
   memset(d, 0, sizeof(*d));
   d->plane = plane_elems(p);
   d->nx = p->nx;
+  d->pitch = hlbm::row_pitch(p->nx);
   d->ny = p->ny;
   d->bcx = p->bc_x;
   d->bcy = p->bc_y;

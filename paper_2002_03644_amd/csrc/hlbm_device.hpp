@@ -46,12 +46,21 @@ constexpr int kPlanes = 10;
 struct DomainArgs {
   long long plane;     // elements per plane (padded)
   int nx, ny, bcx, bcy;
+  int pitch;           // elements per state row (nx rounded up to 64)
   int flags;           // bit 0: Phi by finite differences, bit 1: centred E1, bit 2: no E2
   real mu, sigma, lambda, inv_cv, gm1, e2c, gamma, sgn_eps;
   real rho_ref, theta_ref, log_rho_ref, s_ref;
   real fref[kQ];       // deviation reference populations (zero in the FP64 form)
   real wall_u_lo, wall_u_hi, wall_theta;  // bcy == kBcWall: wall velocities, temperature
 };
+
+// State offset (within a plane) of node i = y nx + x of the dense [ny][nx]
+// order used by the field arrays.
+__device__ __forceinline__ long long state_off(const DomainArgs &d, long long i) {
+  if (d.pitch == d.nx) return i;
+  const int y = (int)(i / d.nx);
+  return (long long)y * d.pitch + (i - (long long)y * d.nx);
+}
 
 struct StepArgs {
   DomainArgs d;
@@ -305,7 +314,7 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
 
   // 32-bit byte offset of virtual row j (x fastest) from the plane bases.
   auto row_off = [&](int j) {
-    return (unsigned)(map_index(y0 - 2 + j, d.ny, d.bcy) * d.nx + cx) * kEl;
+    return (unsigned)(map_index(y0 - 2 + j, d.ny, d.bcy) * d.pitch + cx) * kEl;
   };
 
   // Node state of rows k (s0_*) and k+1 (s1_*) carried from A to B.
@@ -518,7 +527,7 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
       const real lap = ((r_th[t0][ri + 1] + r_th[t0][ri - 1]) + (r_th[tn][ri] + r_th[ts][ri])) -
                        real(4) * r_th[t0][ri];
       const real snew = sc - (advx + advy) + div_fast(d.lambda * lap + cB_phi, cB_rho * cB_th);
-      const unsigned off = (unsigned)((y0 + k - 2) * d.nx + vx) * kEl;
+      const unsigned off = (unsigned)((y0 + k - 2) * d.pitch + vx) * kEl;
 #pragma unroll
       for (int q = 0; q < kQ; ++q) store_stream(dst[q], off, Fo[q]);
       store_stream(dst[9], off, snew);
@@ -655,7 +664,7 @@ __global__ void k_init(InitArgs a) {
     real f[kQ];
     project(A0, rho * ux, rho * uy, Axx, Axy, Ayy, Axxy, Axyy, Axxyy, f);
     const long long P = d.plane;
-    const long long o = (long long)y * d.nx + x;
+    const long long o = (long long)y * d.pitch + x;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) a.dst[q * P + o] = f[q];
     a.dst[9 * P + o] = a.s[i] - d.s_ref;
@@ -689,7 +698,7 @@ __device__ __forceinline__ void wall_node(const WallArgs &a, const int t) {
   const int yw = side ? d.ny - 1 : 0, dir = side ? -1 : 1;
   const real U = side ? d.wall_u_hi : d.wall_u_lo;
   const long long P = d.plane;
-  real *node = a.state + (long long)yw * d.nx + x;
+  real *node = a.state + (long long)yw * d.pitch + x;
   real F[kQ];
 #pragma unroll
   for (int q = 0; q < kQ; ++q) F[q] = node[q * P];
@@ -699,7 +708,7 @@ __device__ __forceinline__ void wall_node(const WallArgs &a, const int t) {
   const real dr = ((F[0] + F[1]) + F[3]) + real(2) * in;
   const real rho = dr + d.rho_ref;
   auto velocity = [&](int y, real &ux, real &uy) {
-    const real *p = a.state + (long long)y * d.nx + x;
+    const real *p = a.state + (long long)y * d.pitch + x;
     real G[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) G[q] = p[q * P];
@@ -764,10 +773,11 @@ __global__ void k_moments(FieldArgs a) {
   const long long n = (long long)d.nx * d.ny, P = d.plane;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
+    const long long o = state_off(d, i);
     real F[kQ];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) F[q] = a.state[q * P + i];
-    const real sv = a.state[9 * P + i];
+    for (int q = 0; q < kQ; ++q) F[q] = a.state[q * P + o];
+    const real sv = a.state[9 * P + o];
     const NodeMoments m = node_moments(F, d);
     if (a.rho) a.rho[i] = m.rho;
     if (a.ux) a.ux[i] = m.jx / m.rho;
@@ -791,13 +801,14 @@ __global__ void k_populations(PopArgs a) {
   const long long n = (long long)d.nx * d.ny, P = d.plane;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
+    const long long o = state_off(d, i);
     if (a.to_state) {
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) a.state[q * P + i] = a.F9[q * n + i] - d.fref[q];
-      a.state[9 * P + i] = a.s[i] - d.s_ref;
+      for (int q = 0; q < kQ; ++q) a.state[q * P + o] = a.F9[q * n + i] - d.fref[q];
+      a.state[9 * P + o] = a.s[i] - d.s_ref;
     } else {
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) a.F9[q * n + i] = a.state[q * P + i] + d.fref[q];
+      for (int q = 0; q < kQ; ++q) a.F9[q * n + i] = a.state[q * P + o] + d.fref[q];
     }
   }
 }
@@ -832,10 +843,11 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(ReduceArgs a) {
   // Fixed per-thread assignment and fixed combine order: deterministic.
   for (long long i = blockIdx.x * (long long)kRedThreads + threadIdx.x; i < n;
        i += (long long)gridDim.x * kRedThreads) {
+    const long long o = state_off(d, i);
     real F[kQ];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) F[q] = a.state[q * P + i];
-    const real sv = a.state[9 * P + i];
+    for (int q = 0; q < kQ; ++q) F[q] = a.state[q * P + o];
+    const real sv = a.state[9 * P + o];
     const NodeMoments m = node_moments(F, d);
     const double rho = (double)m.rho;
     const double ux = (double)m.jx / rho, uy = (double)m.jy / rho;

@@ -11,6 +11,7 @@ static DomainArgs to_device(const HostDomain &h) {
   DomainArgs d;
   d.plane = h.plane;
   d.nx = h.nx;
+  d.pitch = h.pitch;
   d.ny = h.ny;
   d.bcx = h.bcx;
   d.bcy = h.bcy;

@@ -10,7 +10,7 @@ namespace hlbm {
 // to its device argument struct.
 struct HostDomain {
   long long plane;
-  int nx, ny, bcx, bcy, flags;
+  int nx, ny, pitch, bcx, bcy, flags;
   double mu, sigma, lambda, inv_cv, gm1, e2c, gamma, sgn_eps;
   double rho_ref, theta_ref, log_rho_ref, s_ref;
   double fref[9];
@@ -55,18 +55,26 @@ inline TileShape step_tile(int nx, int ny, int tile_w, int tile_h, int elem_size
   return t;
 }
 
-// Elements from one state plane to the next (elem_size 4 or 8).  A node's
-// ten values sit at the same offset in every plane, and the step reads the
-// same row segment from all ten at once.  With a plane size that is a
-// multiple of a large power of two (8192^2 FP32: 256 MiB) those ten segments
-// land on the same HBM channels and banks.  Planes of 4 MiB or more
-// therefore get a stride of a multiple of 128 KiB plus 64 KiB + 256 B (at
-// most 0.2 MiB of padding per plane): 3 % faster at 8192^2 FP32 than the
-// bare 256 MiB stride, 1-2 % at 4096^2 and 6000^2.  Smaller planes keep a
-// 64-element stride.
+// Elements from one state row to the next: nx rounded up to 64, so that every
+// row, and with it every tile's row segment, starts 256-byte aligned (FP32).
+// Rows of other widths lost 5 % (6000 and 14000 columns, rows 64-byte
+// aligned) to 26 % (15446 columns, 24 bytes off a 64-byte boundary) of the
+// step rate of their aligned neighbours.  The columns past nx are never read
+// or written.
+inline int row_pitch(int nx) { return (nx + 63) / 64 * 64; }
+
+// Elements from one state plane to the next (elem_size 4 or 8): pitch x ny
+// rounded up to 64.  A node's ten values sit at the same offset in every
+// plane, and the step reads the same row segment from all ten at once.  With
+// a plane size that is a multiple of a large power of two (8192^2 FP32: 256
+// MiB) those ten segments land on the same HBM channels and banks.  Planes of
+// 4 MiB or more therefore get a stride of a multiple of 128 KiB plus 64 KiB +
+// 256 B (at most 0.2 MiB of padding per plane): 3 % faster at 8192^2 FP32
+// than the bare 256 MiB stride, 1-2 % at 4096^2 and 6000^2.  Smaller planes
+// keep a 64-element stride.
 inline long long plane_stride(int nx, int ny, int elem_size) {
   const size_t es = (size_t)elem_size;
-  const size_t elems = ((size_t)nx * (size_t)ny + 63) / 64 * 64;
+  const size_t elems = ((size_t)row_pitch(nx) * (size_t)ny + 63) / 64 * 64;
   if (elems * es < ((size_t)4 << 20)) return (long long)elems;
   const size_t unit = (size_t)128 << 10;
   const size_t bytes = (elems * es + unit - 1) / unit * unit + ((size_t)64 << 10) + 256;

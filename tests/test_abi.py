@@ -86,20 +86,24 @@ def test_workspace_size_covers_two_state_buffers():
         for nx, ny in ((8192, 8192), (4096, 4), (1, 1), (131, 77)):
             ws = workspace_bytes(_params(nx=nx, ny=ny, dtype=dt))
             assert ws >= 2 * 10 * nx * ny * es
-            # plus at most 192 KiB + 256 B of stride padding per plane
-            assert ws < 2 * 10 * ((nx * ny + 64) * es + 192 * 1024 + 256) + 2 * 2 ** 20
+            # rows padded to 64 elements, plus at most 192 KiB + 256 B of
+            # stride padding per plane
+            pitch = -(-nx // 64) * 64
+            assert ws < 2 * 10 * ((pitch * ny + 64) * es + 192 * 1024 + 256) + 2 * 2 ** 20
 
 
 @pytest.mark.parametrize("dt,es", [("f32", 4), ("f64", 8)])
 def test_large_planes_get_a_stride_off_the_power_of_two(dt, es):
-    """Planes of 4 MiB or more sit 64 KiB + 256 B past a multiple of
-    128 KiB apart, so that a node's ten values do not share HBM channels and
-    banks; smaller planes keep a 64-element stride."""
+    """Rows are padded to 64 elements (256-byte aligned FP32 rows); planes of
+    4 MiB or more sit 64 KiB + 256 B past a multiple of 128 KiB apart, so
+    that a node's ten values do not share HBM channels and banks; smaller
+    planes keep a 64-element stride."""
     from paper_2002_03644_amd import Params
     from paper_2002_03644_amd._lib import lib
     for nx, ny in ((8192, 8192), (4096, 4096), (6000, 6000), (1024, 1024), (131, 77), (1, 1)):
         plane = lib().hlbm_state_bytes(ctypes.byref(Params(nx, ny, dtype=dt).c())) // 10
-        base = -(-nx * ny // 64) * 64 * es
+        pitch = -(-nx // 64) * 64
+        base = -(-pitch * ny // 64) * 64 * es
         if base < 4 * 2 ** 20:
             assert plane == base, (nx, ny)
         else:

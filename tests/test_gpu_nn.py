@@ -214,11 +214,17 @@ def test_correction_moves_only_the_equilibrium():
                           np.array([1e-3, 1e-3, 1e-3, 1e-4])[:, None, None]).astype(np.float32)).cuda()
     B.correct(x, d, conserve=False)
     after = B.save_state()
-    n = 32 * 32
-    plane = ((n + 63) // 64) * 64
-    # a saved state is the current buffer: ten planes of FP32 deviations
-    s0 = snap.view(torch.float32)[: 10 * plane].reshape(10, plane)[:, :n].double().cpu().numpy()
-    s1 = after.view(torch.float32)[: 10 * plane].reshape(10, plane)[:, :n].double().cpu().numpy()
+    nx = ny = 32
+    n = nx * ny
+    # a saved state is the current buffer: ten planes of FP32 deviations,
+    # rows padded to 64 elements, planes to a multiple of 64
+    pitch = -(-nx // 64) * 64
+    plane = -(-(pitch * ny) // 64) * 64
+
+    def dense(buf):
+        a = buf.view(torch.float32)[: 10 * plane].reshape(10, plane)[:, : pitch * ny]
+        return a.reshape(10, ny, pitch)[:, :, :nx].reshape(10, n).double().cpu().numpy()
+    s0, s1 = dense(snap), dense(after)
     xc = x.double().cpu().numpy()[:, 0]
     dc = d.double().cpu().numpy()[:, 0]
     r2, u2, v2, t2 = C.apply_correction(xc[0], xc[1], xc[2], xc[3], dc, conserve=False)
