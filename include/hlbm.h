@@ -105,10 +105,11 @@ typedef struct hlbm_handle hlbm_handle;
 size_t hlbm_workspace_bytes(const hlbm_params *p);
 
 /* Bytes of one raw state copy (ten planes, storage format) for
- * hlbm_save_state / hlbm_load_state; 0 if invalid.  Host-only.  Planes of
- * 4 MiB or more are padded to a stride 64 KiB + 256 B past a multiple of
- * 128 KiB, so this exceeds 10 nx ny element sizes by up to 1.9 MiB; a copy
- * is only meaningful to a domain with the same nx, ny and dtype. */
+ * hlbm_save_state / hlbm_load_state; 0 if invalid.  Host-only.  State rows
+ * are padded to a multiple of 64 elements and planes of 4 MiB or more to a
+ * stride 64 KiB + 256 B past a multiple of 128 KiB, so this is
+ * 10 x (pitch ny + padding) element sizes with pitch = nx rounded up to 64;
+ * a copy is only meaningful to a domain with the same nx, ny and dtype. */
 size_t hlbm_state_bytes(const hlbm_params *p);
 
 /* Check parameters without touching the GPU: HLBM_OK or HLBM_EINVAL. */
