@@ -101,18 +101,19 @@ def vortex(nx, ny, xc, yc, R, mach_inf, mach_v, angle=0.0, gamma=1.4,
     return rho, ux, uy, theta
 
 
-def shear_wave(n, a0, u_inf, theta, rho=1.0, width=2, axis="y"):
-    """u_x = a0 sin(2 pi y / L), u_y = u_inf, uniform p and T (Sec. 4.1).
-    Quasi-1D: ``width`` columns across, ``n`` points per wavelength."""
+def shear_wave(n, a0, u_inf, theta, rho=1.0, width=2, axis="y", shift=0.0):
+    """u_x = a0 sin(2 pi (y + shift) / L), u_y = u_inf, uniform p and T
+    (Sec. 4.1).  Quasi-1D: ``width`` columns across, ``n`` points per
+    wavelength.  shift = 0.5 puts the zeros of u_x half-way between nodes."""
     if axis == "y":
         nx, ny = width, n
         _, Y = _grid(nx, ny)
-        ux = a0 * np.sin(2 * np.pi * Y / n)
+        ux = a0 * np.sin(2 * np.pi * (Y + shift) / n)
         uy = np.full((ny, nx), u_inf)
-    else:  # transposed: u_y = a0 sin(2 pi x / L), u_x = u_inf
+    else:  # transposed: u_y = a0 sin(2 pi (x + shift) / L), u_x = u_inf
         nx, ny = n, width
         X, _ = _grid(nx, ny)
-        uy = a0 * np.sin(2 * np.pi * X / n)
+        uy = a0 * np.sin(2 * np.pi * (X + shift) / n)
         ux = np.full((ny, nx), u_inf)
     return np.full((ny, nx), rho), ux, uy, np.full((ny, nx), theta)
 
@@ -180,6 +181,37 @@ def riemann(nx, ny, left, right, x_split=None, theta_scale=0.2):
 def sod(nx, ny, theta_scale=0.2):
     """Standard Sod states (rho, u, p) = (1, 0, 1) | (0.125, 0, 0.1)."""
     return riemann(nx, ny, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), theta_scale=theta_scale)
+
+
+# The shock tube of Sec. 5.2 in lattice units.  Air, r = 287.15 J/(kg K) (the
+# paper's value), T_inf = 300 K on both sides, T_r = 1460 K, p_inf = 101325
+# Pa, a 1 m tube of 401 points (dx = 1/400 m), mu = 1e-5 kg/(m s).  The
+# velocity unit is C_0 = sqrt(r T_r / c_s^2) and the density unit rho_inf, so
+# mu_lattice = mu / (rho_inf dx C_0).
+PAPER_TUBE = dict(r=287.15, T_inf=300.0, T_r=1460.0, p_inf=101325.0, length=1.0, nx=401,
+                  mu=1e-5)
+
+
+def paper_tube_mu(nx=PAPER_TUBE["nx"]):
+    """Lattice dynamic viscosity of the Sec. 5.2 tube on nx points."""
+    c = PAPER_TUBE
+    dx = c["length"] / (nx - 1)
+    c0 = math.sqrt(c["r"] * c["T_r"] / CS2)
+    rho_inf = c["p_inf"] / (c["r"] * c["T_inf"])
+    return c["mu"] / (rho_inf * dx * c0)
+
+
+def paper_shock_tube(nx=PAPER_TUBE["nx"], ny=2):
+    """Sec. 5.2: (rho, u, p) = (3 rho_inf, 0, 3 p_inf) for x < 0.5 m and
+    (rho_inf, 0, p_inf) beyond, one temperature T_inf throughout, so theta =
+    T_inf / T_r on both sides and rho = 3 | 1 in units of rho_inf.  The split
+    falls between node (nx - 1) / 2 - 1 and (nx - 1) / 2 (x_i = i dx)."""
+    c = PAPER_TUBE
+    theta = c["T_inf"] / c["T_r"]
+    X, _ = _grid(nx, ny)
+    dx = c["length"] / (nx - 1)
+    rho = np.where(X * dx < 0.5 * c["length"], 3.0, 1.0)
+    return rho, np.zeros_like(rho), np.zeros_like(rho), np.full_like(rho, theta)
 
 
 def rankine_hugoniot(mach, gamma=1.4):

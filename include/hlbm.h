@@ -56,7 +56,10 @@ typedef enum { HLBM_PHI_LBM = 0, HLBM_PHI_FD = 1 } hlbm_phi;
 /* Parameters of one domain.  A zero-initialised struct plus nx, ny, gamma,
  * prandtl and the reference state selects the present model. */
 typedef struct {
-  int32_t nx, ny;       /* grid size, >= 1 each, 9 * nx * ny < 2^31 */
+  int32_t nx, ny;       /* grid size, >= 1 each, 9 * nx * ny < 2^31; with rows padded
+                           to pitch = nx rounded up to 64, also pitch * ny < 2^31
+                           and pitch * ny * element size < 2^32 (the step
+                           addresses a plane with 32-bit byte offsets) */
   int32_t bc_x, bc_y;   /* hlbm_bc on both sides of that axis: periodic wrap,
                            or zero-gradient extrapolation (the neighbour index
                            is clamped into the grid, so ghost nodes carry the
@@ -95,6 +98,12 @@ typedef struct {
                             where neighbouring temperatures differ by ~1e-6 of
                             theta (FP32 thermal Couette 2 x 100: error 3e-3 ->
                             2e-4 of the temperature rise, ~1 % slower step) */
+  int32_t feq_order;    /* 0 or 4: equilibrium and off-equilibrium populations
+                           carry the fourth-order Hermite term xxyy (present
+                           model, Sec. 2.3); 3: truncated at third order, as
+                           in the original model the paper compares against
+                           (Sec. 2.3, Table 1); with e1_centred = e2_off = 1
+                           this is that model */
 } hlbm_params;
 
 typedef struct hlbm_handle hlbm_handle;
@@ -236,11 +245,17 @@ int hlbm_batch_status(hlbm_batch *b, int32_t *host_flags, hlbm_stream_t stream);
  * Synchronises `stream`. */
 int hlbm_batch_set_tile(hlbm_batch *b, int32_t tile_w, int32_t tile_h, hlbm_stream_t stream);
 
-/* Time `steps` steps for every tile shape in {64, 128, 192, 256} x {4, 8, 16,
- * 32, 64, 128}, keep the fastest and report it.  Advances the domains; save and load
- * the state around it to keep them.  Synchronises `stream`. */
-int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, int32_t *host_best_w, int32_t *host_best_h,
-                        hlbm_stream_t stream);
+/* Time `steps` steps (after one untimed step) for every tile shape in
+ * {64, 128, 192, 256} x {4, 8, 16, 32, 64, 128}, twice each, keep the fastest
+ * and report it.  scratch: a device buffer of hlbm_batch_state_bytes(b) bytes
+ * owned by the caller; the state at entry is saved there and loaded again
+ * (divergence flags cleared) before every trial, so all shapes time the same
+ * work, and once more at the end: the domains, their flags and the step
+ * count are left as they were (the graphs are dropped and re-captured on the
+ * next hlbm_batch_step).  HLBM_EINVAL if scratch is NULL.  Synchronises
+ * `stream`. */
+int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, void *scratch, int32_t *host_best_w,
+                        int32_t *host_best_h, hlbm_stream_t stream);
 
 /* Raw state of all domains (for checkpoint, or around hlbm_batch_autotune);
  * load also clears the divergence flags. */

@@ -39,7 +39,7 @@ class CParams(ctypes.Structure):
                 ("rho_ref", ctypes.c_double), ("theta_ref", ctypes.c_double),
                 ("sgn_eps", ctypes.c_double), ("wall_ux_lo", ctypes.c_double),
                 ("wall_ux_hi", ctypes.c_double), ("wall_theta", ctypes.c_double),
-                ("precise_theta", ctypes.c_int32)]
+                ("precise_theta", ctypes.c_int32), ("feq_order", ctypes.c_int32)]
 
 
 _lib = None
@@ -81,7 +81,7 @@ def lib():
             "hlbm_batch_moments": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
             "hlbm_batch_status": (ctypes.c_int, [vp, ctypes.POINTER(i32), vp]),
             "hlbm_batch_set_tile": (ctypes.c_int, [vp, i32, i32, vp]),
-            "hlbm_batch_autotune": (ctypes.c_int, [vp, i32, ctypes.POINTER(i32),
+            "hlbm_batch_autotune": (ctypes.c_int, [vp, i32, vp, ctypes.POINTER(i32),
                                                    ctypes.POINTER(i32), vp]),
             "hlbm_batch_state_bytes": (sz, [vp]),
             "hlbm_batch_save_state": (ctypes.c_int, [vp, vp, vp]),
@@ -158,6 +158,9 @@ class Params:
     # theta - theta_ref computed accurately relative to the deviation (slow
     # diffusive flows; about 1 % slower)
     precise_theta: bool = False
+    # 4: fourth-order Hermite expansion (present model); 3: truncated at third
+    # order (the original model, with e1_centred and e2_off)
+    feq_order: int = 4
 
     def c(self) -> CParams:
         return CParams(self.nx, self.ny, BC[self.bc_x], BC[self.bc_y],
@@ -165,7 +168,7 @@ class Params:
                        int(self.e1_centred), int(self.e2_off), int(self.tile_w), int(self.tile_h),
                        self.gamma, self.prandtl, self.mu, self.sigma, self.rho_ref, self.theta_ref,
                        self.sgn_eps, self.wall_ux_lo, self.wall_ux_hi, self.wall_theta,
-                       int(self.precise_theta))
+                       int(self.precise_theta), int(self.feq_order))
 
     @property
     def torch_dtype(self):
@@ -507,7 +510,8 @@ class BatchSolver:
         return hashlib.sha256(key.encode()).hexdigest()[:20]
 
     def autotune(self, steps=10, cache_path=None):
-        """Pick the fastest tile shape by timing (state restored afterwards).
+        """Pick the fastest tile shape by timing; every shape is timed from the
+        same state, which is restored afterwards (flags and step count too).
         With ``cache_path`` the choice is read from / written to a JSON file
         keyed by the batch's domain sizes and dtype."""
         import json
@@ -520,12 +524,16 @@ class BatchSolver:
                 w, h = cache[sig]
                 self.set_tile(w, h)
                 return int(w), int(h)
-        snap = self.save_state()
+        import torch
+        scratch = torch.empty(lib().hlbm_batch_state_bytes(self.h), dtype=torch.uint8,
+                              device=self.device)
         bw, bh = ctypes.c_int32(0), ctypes.c_int32(0)
         self._enter()
-        _check(lib().hlbm_batch_autotune(self.h, int(steps), ctypes.byref(bw), ctypes.byref(bh),
-                                         _stream(self.stream)), "hlbm_batch_autotune")
-        self.load_state(snap)
+        _check(lib().hlbm_batch_autotune(self.h, int(steps), _ptr(scratch), ctypes.byref(bw),
+                                         ctypes.byref(bh), _stream(self.stream)),
+               "hlbm_batch_autotune")
+        self._leave()
+        del scratch
         if cache_path:
             cache[sig] = [bw.value, bh.value]
             os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)

@@ -114,8 +114,9 @@ __global__ __launch_bounds__(kCorrThreads) void k_corr_apply(CorrArgs a) {
     const real th2 = th + dth;
     const EqCoef e1 = eq_coef(r, u, v, th), e2 = eq_coef(r2, u2, v2, th2);
     real df[kQ];
+    const real dxxyy = (d.flags & kFlagFeq3) ? real(0) : e2.Axxyy - e1.Axxyy;
     project(e2.A0 - e1.A0, e2.Ax - e1.Ax, e2.Ay - e1.Ay, e2.Axx - e1.Axx, e2.Axy - e1.Axy,
-            e2.Ayy - e1.Ayy, e2.Axxy - e1.Axxy, e2.Axyy - e1.Axyy, e2.Axxyy - e1.Axxyy, df);
+            e2.Ayy - e1.Ayy, e2.Axxy - e1.Axxy, e2.Axyy - e1.Axyy, dxxyy, df);
     const long long o = state_off(d, i);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) st[q * P + o] += df[q];

@@ -47,7 +47,8 @@ struct DomainArgs {
   long long plane;     // elements per plane (padded)
   int nx, ny, bcx, bcy;
   int pitch;           // elements per state row (nx rounded up to 64)
-  int flags;           // bit 0: Phi by finite differences, bit 1: centred E1, bit 2: no E2
+  int flags;           // bit 0: Phi by finite differences, bit 1: centred E1, bit 2: no E2,
+                       // bit 3: precise theta, bit 4: third-order expansion
   real mu, sigma, lambda, inv_cv, gm1, e2c, gamma, sgn_eps;
   real rho_ref, theta_ref, log_rho_ref, s_ref;
   real fref[kQ];       // deviation reference populations (zero in the FP64 form)
@@ -74,6 +75,10 @@ struct StepArgs {
 
 constexpr int kFlagPhiFD = 1, kFlagE1Centred = 2, kFlagE2Off = 4;
 constexpr int kFlagPreciseTheta = 8;  // theta - theta_ref from expm1 / log1p (see node_dtheta)
+// Hermite expansion truncated at third order (the original model of Sec. 2.3):
+// the xxyy coefficient of every projected population, equilibrium and
+// off-equilibrium alike, is zero (the deviation reference drops it too).
+constexpr int kFlagFeq3 = 16;
 constexpr int kBcWall = 2;  // rows y = 0 and y = ny - 1 are walls (ghosts beyond them clamp)
 
 // ---------------------------------------------------------------- helpers
@@ -469,7 +474,9 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
         const real rc = rho * c;
         const real Axxy = ruxx * uy + rc * uy + om * a1xxy;
         const real Axyy = ruyy * ux + rc * ux + om * a1xyy;
-        const real Axxyy = ruxx * uy * uy + rc * (ux * ux + uy * uy) + drc2 + om * a1xxyy;
+        const real Axxyy = (d.flags & kFlagFeq3)
+                               ? real(0)
+                               : ruxx * uy * uy + rc * (ux * ux + uy * uy) + drc2 + om * a1xxyy;
         real f[kQ];
         project(s0_dr, rux, ruy, Axx, Axy, Ayy, Axxy, Axyy, Axxyy, f);
         r_f0[k & 1][0][ri] = f[1];
@@ -565,7 +572,11 @@ __global__ __launch_bounds__(CW + 64) void k_step(StepArgs a) {
 // Batched step: a persistent grid walks a list of (domain, tile) items,
 // statically round-robin (no atomics: the launch can be captured and
 // replayed).  Items of a domain whose divergence flag is set are skipped, so
-// a diverged domain freezes while the others go on.
+// a diverged domain freezes while the others go on.  The flag can be set by
+// another workgroup at any moment, so the skip is decided once per item for
+// the whole workgroup (a barrier with an OR over the threads): waves that
+// read the flag at different times would otherwise disagree, and the
+// barriers inside the sweep would then pair up across different items.
 struct BatchArgs {
   const DomainArgs *doms;
   const long long *offs;  // element offset of each domain's state in a buffer
@@ -583,7 +594,10 @@ __global__ __launch_bounds__(CW + 64) void k_step_batch(BatchArgs a) {
   for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
     const int4 w = a.items[it];
     const int dm = __builtin_amdgcn_readfirstlane(w.x);
-    if (__builtin_amdgcn_readfirstlane(a.status[dm]) != 0u) continue;  // uniform skip
+    // one decision per workgroup; the barrier also keeps the previous item's
+    // last ring reads ahead of this item's first writes
+    const int frozen = threadIdx.x == 0 ? (int)(__atomic_load_n(&a.status[dm], __ATOMIC_RELAXED) != 0u) : 0;
+    if (__syncthreads_or(frozen)) continue;
     const DomainArgs d = a.doms[dm];
     const long long off = a.offs[dm];
     sweep_tile<CW>(d, a.src_buf + off, a.dst_buf + off, a.status + dm, a.rows,
@@ -659,8 +673,9 @@ __global__ void k_init(InitArgs a) {
     const real Axy = rho * ux * uy + a1xy;
     const real Axxy = rho * ux * ux * uy + rc * uy + a1xxy;
     const real Axyy = rho * ux * uy * uy + rc * ux + a1xyy;
-    const real Axxyy = rho * ux * ux * uy * uy + rc * (ux * ux + uy * uy) +
-                       (rc * c - d.rho_ref * cref * cref) + a1xxyy;
+    const real Axxyy = (d.flags & kFlagFeq3) ? real(0)
+                                             : rho * ux * ux * uy * uy + rc * (ux * ux + uy * uy) +
+                                                   (rc * c - d.rho_ref * cref * cref) + a1xxyy;
     real f[kQ];
     project(A0, rho * ux, rho * uy, Axx, Axy, Ayy, Axxy, Axyy, Axxyy, f);
     const long long P = d.plane;
@@ -746,7 +761,7 @@ __device__ __forceinline__ void wall_node(const WallArgs &a, const int t) {
   const real Axy = a1xy;
   const real Axxy = a1xxy;
   const real Axyy = rc * U + a1xyy;
-  const real Axxyy = rc * U * U + drc2 + a1xxyy;
+  const real Axxyy = (d.flags & kFlagFeq3) ? real(0) : rc * U * U + drc2 + a1xxyy;
   real f[kQ];
   project(dr, rho * U, real(0), Axx, Axy, Ayy, Axxy, Axyy, Axxyy, f);
 #pragma unroll

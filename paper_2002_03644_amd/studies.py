@@ -6,7 +6,7 @@ one temperature for every Mach number (theta = 240/1183, the paper's
 T/T_r = 300 / 1478.75), advected along x for 50 convective times L / u_inf
 -- after which the exact solution is the initial field again -- for a grid
 of HRR blends sigma and Mach numbers, and, at sigma = 0, the original model
-(centred E1, no E2).  Per run: the L2 error of the pressure relative to the
+(equilibrium truncated at third order, centred E1, no E2).  Per run: the L2 error of the pressure relative to the
 vortex's pressure perturbation, ||p - p_0||_2 / ||p_0 - p_inf||_2, a
 divergence flag (non-finite or non-physical state), and an energy flag set
 when the largest total-energy density p / (gamma - 1) + rho |u|^2 / 2 grew
@@ -67,7 +67,8 @@ def sigma_mach_map(machs=None, sigmas=None, n=200, conv_times=50.0, beta=0.1, mu
                       theta_inf=theta, periodic_images=True)
         models = [("present", s) for s in sigmas] + ([("original", 0.0)] if original else [])
         params = [Params(n, n, dtype=dtype, gamma=gamma, mu=mu, sigma=s, theta_ref=theta,
-                         e1_centred=(m == "original"), e2_off=(m == "original"))
+                         e1_centred=(m == "original"), e2_off=(m == "original"),
+                         feq_order=3 if m == "original" else 4)
                   for m, s in models]
         B = BatchSolver(params, [f] * len(models), device=device)
         B.autotune(steps=10)
@@ -127,37 +128,52 @@ def map_summary(res: MapResult):
 
 
 
-def acoustic_pulse(n=201, R=6.0, amp_pa=10.0, p_inf_pa=101323.0, t_frac=0.4, gamma=1.4,
-                   theta=hi.THETA_PAPER, mu=1.5e-6, dtype="f64", device="cuda"):
-    """The Gaussian acoustic pulse of Sec. 5.1 at Ma = 0 (sigma 0.95, centred)
-    and Ma = 1 (sigma 0, started at x = n / 10 so both end at the centre),
-    one batch of the two on a periodic n x n box: p = p_inf (1 + A
-    exp(-r^2 / (2 R^2))) with A = amp_pa / p_inf_pa, isentropic rho and
-    theta, u_x = Ma c.  Runs round(t_frac n / c) steps.  Returns, per Mach
-    number, the pressure perturbation p - p_inf [n][n] (FP64 numpy), its
-    initial centre (x0, y0) in cells, the mean velocity, and the steps."""
+def acoustic_pulse_cases(n=201, R=6.0, amp_pa=10.0, p_inf_pa=101323.0, t_frac=0.4, gamma=1.4,
+                         theta=hi.THETA_PAPER, mu=1.5e-6):
+    """Set-up of the Gaussian acoustic pulse of Sec. 5.1 at Ma = 0 (sigma
+    0.95, centred) and Ma = 1 (sigma 0, started at x = n / 10 so both end at
+    the centre) on a periodic n x n box: p = p_inf (1 + A exp(-r^2 / (2
+    R^2))) with A = amp_pa / p_inf_pa, isentropic rho and theta, u_x = Ma c.
+    Returns (steps, cases); steps = round(t_frac n / c); each case is a dict
+    with mach, sigma, x0, y0, the parameter keywords of the domain (mu,
+    sigma, gamma) and its host fields (rho, ux, uy, theta)."""
     c = hi.sound_speed(gamma, theta)
     steps = int(round(t_frac * n / c))
     p_inf = hi.CS2 * theta
     X, Y = np.meshgrid(np.arange(n, dtype=np.float64), np.arange(n, dtype=np.float64))
-    cases = [(0.0, 0.95, n // 2), (1.0, 0.0, n // 10)]
-    params, fields = [], []
-    for mach, sigma, xc in cases:
+    cases = []
+    for mach, sigma, xc in ((0.0, 0.95, n // 2), (1.0, 0.0, n // 10)):
         dx = (X - xc + n / 2) % n - n / 2
         dy = (Y - n // 2 + n / 2) % n - n / 2
         p = p_inf * (1.0 + amp_pa / p_inf_pa * np.exp(-(dx * dx + dy * dy) / (2.0 * R * R)))
         rho = (p / p_inf) ** (1.0 / gamma)
-        fields.append((rho, np.full((n, n), mach * c), np.zeros((n, n)), p / (rho * hi.CS2)))
-        params.append(Params(n, n, dtype=dtype, gamma=gamma, mu=mu, sigma=sigma, theta_ref=theta))
-    B = BatchSolver(params, fields, device=device)
+        cases.append({"mach": mach, "sigma": sigma, "x0": float(xc), "y0": float(n // 2),
+                      "kw": dict(gamma=gamma, mu=mu, sigma=sigma),
+                      "fields": (rho, np.full((n, n), mach * c), np.zeros((n, n)),
+                                 p / (rho * hi.CS2)),
+                      "u": mach * c, "amp": p_inf * amp_pa / p_inf_pa, "c": c, "R": R,
+                      "p_inf": p_inf})
+    return steps, cases
+
+
+def acoustic_pulse(n=201, dtype="f64", device="cuda", **kw):
+    """Both pulses of acoustic_pulse_cases as one batch of two domains,
+    advanced on the GPU.  Returns, per Mach number, the pressure perturbation
+    p - p_inf [n][n] (FP64 numpy), the final fields (rho, ux, uy, s, theta),
+    the initial centre (x0, y0) in cells, the mean velocity and the steps."""
+    theta = kw.get("theta", hi.THETA_PAPER)
+    steps, cases = acoustic_pulse_cases(n, **kw)
+    params = [Params(n, n, dtype=dtype, theta_ref=theta, **cs["kw"]) for cs in cases]
+    B = BatchSolver(params, [cs["fields"] for cs in cases], device=device)
     B.step(steps, graph=True)
     mom = B.moments()
     out = {}
-    for k, (mach, sigma, xc) in enumerate(cases):
+    for k, cs in enumerate(cases):
         d = {key: v.double().cpu().numpy() for key, v in mom[k].items()}
-        out[mach] = {"p_prime": _pressure(d["rho"], d["theta"]) - p_inf, "x0": float(xc),
-                     "y0": float(n // 2), "u": mach * c, "steps": steps, "sigma": sigma,
-                     "amp": p_inf * amp_pa / p_inf_pa, "c": c, "R": R}
+        out[cs["mach"]] = {"p_prime": _pressure(d["rho"], d["theta"]) - cs["p_inf"],
+                           "fields": d, "x0": cs["x0"], "y0": cs["y0"], "u": cs["u"],
+                           "steps": steps, "sigma": cs["sigma"], "amp": cs["amp"],
+                           "c": cs["c"], "R": cs["R"]}
     return out
 
 

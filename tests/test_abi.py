@@ -58,6 +58,29 @@ def test_validate_rejects(bad):
     assert workspace_bytes(p) == 0
 
 
+def test_validate_bounds_padded_plane_offsets():
+    """The step addresses a plane with (y pitch + x) in 32-bit int and its
+    byte offset in 32 bits, with pitch = nx rounded up to 64.  Narrow, tall
+    grids pass the 9 nx ny < 2^31 element bound but not this one: at nx = 1
+    the pitch is 64, so FP64 allows ny < 2^23 and FP32 ny < 2^24."""
+    from paper_2002_03644_amd import HLBM_EINVAL, HLBM_OK, validate
+    assert validate(_params(nx=1, ny=(1 << 23) - 1, dtype="f64")) == HLBM_OK
+    assert validate(_params(nx=1, ny=1 << 23, dtype="f64")) == HLBM_EINVAL
+    assert validate(_params(nx=1, ny=(1 << 24) - 1, dtype="f32")) == HLBM_OK
+    assert validate(_params(nx=1, ny=1 << 24, dtype="f32")) == HLBM_EINVAL
+    # 16 x 10M in FP64: 9 nx ny < 2^31 holds, the padded plane is 4.8 GiB
+    assert 9 * 16 * 10_000_000 < 2 ** 31
+    assert validate(_params(nx=16, ny=10_000_000, dtype="f64")) == HLBM_EINVAL
+    # a wide grid near the element bound is accepted
+    assert validate(_params(nx=8192, ny=29000)) == HLBM_OK
+
+
+@pytest.mark.parametrize("order,ok", [(0, True), (3, True), (4, True), (2, False), (5, False)])
+def test_validate_feq_order(order, ok):
+    from paper_2002_03644_amd import HLBM_EINVAL, HLBM_OK, validate
+    assert validate(_params(feq_order=order)) == (HLBM_OK if ok else HLBM_EINVAL)
+
+
 def test_wall_parameters_validated_on_the_host():
     from paper_2002_03644_amd import HLBM_EINVAL, HLBM_OK, validate
     ok = dict(bc_y="wall", wall_theta=0.2, wall_ux_hi=0.1)

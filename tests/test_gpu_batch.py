@@ -164,6 +164,7 @@ def test_autotune_restores_state_and_caches(tmp_path):
     w, h = B.autotune(steps=2, cache_path=cache)
     assert w in (64, 128, 192, 256) and h in (4, 8, 16, 32, 64, 128)
     after = [m["rho"] for m in B.moments()]
+    assert B.steps == 4 and B.status()[0] == 0
     for a, b in zip(before, after):
         assert torch.equal(a, b)
     with open(cache) as fh:
@@ -200,3 +201,41 @@ def test_batch_256_domains_seed0():
         S = Solver(params[k], *fields[k][:3], theta=fields[k][3])
         S.step(20)
         assert torch.equal(S.moments()["rho"], mb[k]["rho"]), k
+
+
+def test_divergence_mid_launch_leaves_healthy_domains_bitwise():
+    """Domains that diverge while the same launch is sweeping large healthy
+    domains: a large one whose CFL is far above 1 in a patch (it diverges
+    within the first steps, while its own tiles are still being swept by
+    other workgroups) and a small one that diverges at once.  The skip of a
+    frozen domain's items is decided per workgroup, so no tile of a healthy
+    domain may change: every healthy domain is bitwise equal to its single
+    run, at several tile shapes."""
+    shapes = [(700, 520), (640, 610), (512, 480), (900, 300), (96, 80), (450, 470)]
+    poisoned = {1: "patch", 4: "all"}
+    params, fields = [], []
+    for k, (nx, ny) in enumerate(shapes):
+        th = hi.theta_for_cfl(0.6)
+        f = hi.vortex(nx, ny, nx / 2, ny / 2, 12, 0.4, 0.05, theta_inf=th, angle=0.7 * k)
+        if poisoned.get(k) == "patch":
+            ux = f[1].copy()
+            ux[ny // 3: ny // 3 + 20, nx // 2: nx // 2 + 20] += 3.0
+            f = (f[0], ux, f[2], f[3])
+        elif poisoned.get(k) == "all":
+            f = (f[0], f[1] + 3.0, f[2], f[3])
+        fields.append(f)
+        params.append(Params(nx, ny, dtype="f32", mu=1e-3, sigma=0.2, theta_ref=th))
+    healthy = [k for k in range(len(shapes)) if k not in poisoned]
+    for tw, th_ in ((128, 16), (192, 8), (64, 4)):
+        ps = [dataclasses.replace(p, tile_w=tw, tile_h=th_) for p in params]
+        B = BatchSolver(ps, fields)
+        B.set_tile(tw, th_)
+        B.step(12, graph=True)
+        bad, flags = B.status()
+        assert set(np.nonzero(flags)[0]) == set(poisoned), (tw, th_, flags)
+        mb = B.moments()
+        ms = singles([ps[k] for k in healthy], [fields[k] for k in healthy], 12)
+        for j, k in enumerate(healthy):
+            for key in ("rho", "ux", "uy", "s"):
+                assert torch.equal(mb[k][key], ms[j][key]), (tw, th_, k, key)
+        del B

@@ -3,10 +3,17 @@ and the batch coupling against the FP64 oracle (oracle/cnn_oracle.py).
 
 The oracle's stored-precision passes round to BF16 exactly where the GPU
 stores BF16 (standardised input, weights, hidden activations, propagated
-gradients); the remaining difference is FP32 accumulation against FP64 plus
-the rare BF16 rounding decision that the two accumulations place on
-opposite sides of a tie, hence relative L2 tolerances of 1e-3 on outputs and
-gradients (measured: 1e-5 to 1e-7 on the gradients)."""
+gradients).  What remains is FP32 accumulation against FP64 and the rare
+BF16 rounding decision that the two accumulations place on opposite sides
+of a boundary (a tie flip, one BF16 spacing of a stored value).  The network
+outputs and the parameter gradients are therefore compared element by
+element: each element must lie within one BF16 spacing of the oracle's value
+(2^(e - 7) for a value in [2^e, 2^(e + 1))), except for a counted set of
+outliers -- elements whose value is small against the terms it sums, where
+a tie flip or the accumulation order moves it by more than its own spacing
+-- which must be at most 1 % of the elements and each within one BF16 spacing
+of the absolute sum of the terms (sum |w h| + |b| for an output, sum over
+pixels of |activation| |gradient| for a weight gradient)."""
 import numpy as np
 import pytest
 
@@ -54,6 +61,30 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def bf16_spacing(a):
+    """Spacing of BF16 numbers at |a|: 2^(e - 7) for |a| in [2^e, 2^(e + 1))."""
+    a = np.abs(np.asarray(a, dtype=np.float64))
+    e = np.floor(np.log2(np.maximum(a, 1e-300)))
+    return np.where(a > 0, 2.0 ** (e - 7), 0.0)
+
+
+def check_elementwise(got, want, abs_sum, what, max_outlier_frac=0.01):
+    """Every element within one BF16 spacing of the oracle value, or a
+    counted outlier within one BF16 spacing of its absolute sum."""
+    err = np.abs(got - want)
+    inside = err <= bf16_spacing(want)
+    out = ~inside
+    n_out = int(out.sum())
+    frac = n_out / err.size
+    worst = float((err[out] / bf16_spacing(abs_sum[out])).max()) if n_out else 0.0
+    ratio = float((err / np.maximum(bf16_spacing(want), 1e-300)).max())
+    print(f"{what}: {err.size} elements, {n_out} beyond one spacing of the value "
+          f"({100 * frac:.3f} %), worst outlier {worst:.3f} spacings of its absolute sum, "
+          f"largest error {ratio:.3g} spacings of the value")
+    assert frac <= max_outlier_frac, (what, n_out, err.size)
+    assert (err[out] <= bf16_spacing(abs_sum[out])).all(), (what, worst)
+
+
 def make_net(B, H, W, params):
     net = CNN(B, H, W, C.flatten(params).astype(np.float32))
     net.set_norm(*NORM)
@@ -66,11 +97,20 @@ def test_forward_matches_oracle(B, H, W):
     x, _ = fields(B, H, W, 2)
     net = make_net(B, H, W, params)
     y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
-    ys, _ = C.forward_stored([(w, b) for w, b in params], standardise(x, NORM[0], NORM[1]))
-    yo = ys.transpose(0, 3, 1, 2) * NORM[3][None, :, None, None] + NORM[2][None, :, None, None]
+    xs = standardise(x, NORM[0], NORM[1])
+    ys, acts = C.forward_stored([(w, b) for w, b in params], xs)
+    # absolute sum of the last layer's terms, per output element
+    w3, b3 = params[2]
+    s3 = C.conv3x3(np.abs(acts[2]), np.abs(C.bf16(w3)), np.abs(b3))
+    # compare in standardised units (the de-standardisation is one FP32 FMA)
+    std = NORM[3][None, :, None, None].astype(np.float64)
+    mean = NORM[2][None, :, None, None].astype(np.float64)
+    y_std = ((y - mean) / std).transpose(0, 2, 3, 1)
+    check_elementwise(y_std, ys, s3, f"forward {B}x{H}x{W}")
+    # and, in raw units, a relative L2 summary
+    yo = ys.transpose(0, 3, 1, 2) * std + mean
     for c in range(4):
-        e = rel(y[:, c] - NORM[2][c], yo[:, c] - NORM[2][c])
-        assert e < 1e-3, (c, e)
+        assert rel(y[:, c] - NORM[2][c], yo[:, c] - NORM[2][c]) < 1e-3
 
 
 @pytest.mark.parametrize("B,H,W", [(3, 12, 64), (2, 36, 32), (1, 256, 256)])
@@ -80,13 +120,24 @@ def test_gradients_match_oracle(B, H, W):
     net = make_net(B, H, W, params)
     loss = net.loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
     g = C.unflatten(net.grads().cpu().numpy().astype(np.float64))
-    lo, go = C.loss_and_grads_stored(params, standardise(x, NORM[0], NORM[1]),
-                                     standardise(t, NORM[2], NORM[3]))
+    xs = standardise(x, NORM[0], NORM[1])
+    ts = standardise(t, NORM[2], NORM[3])
+    lo, go = C.loss_and_grads_stored(params, xs, ts)
     assert float(loss.item()) == pytest.approx(lo, rel=1e-3)
-    for k in range(3):
+    # absolute sums of the gradient sums over the pixels: the oracle's stored
+    # activations and stored back-propagated gradients, in absolute value
+    y, acts = C.forward_stored(params, xs)
+    gk = C.bf16(2.0 * (y - ts) / y.size)
+    for k in (2, 1, 0):
+        wb = C.bf16(params[k][0])
+        _, sw, sb = C.conv3x3_grad(np.abs(acts[k]), np.abs(wb), np.abs(gk))
+        check_elementwise(g[k][0], go[k][0], sw, f"dW{k + 1} {B}x{H}x{W}")
+        check_elementwise(g[k][1], go[k][1], sb, f"db{k + 1} {B}x{H}x{W}")
         ew, eb = rel(g[k][0], go[k][0]), rel(g[k][1], go[k][1])
-        print(f"layer {k + 1}: dW rel {ew:.2e}, db rel {eb:.2e}")
-        assert ew < 1e-3 and eb < 1e-3, (k, ew, eb)
+        print(f"layer {k + 1}: dW rel L2 {ew:.2e}, db rel L2 {eb:.2e}")
+        if k > 0:
+            gx, _, _ = C.conv3x3_grad(acts[k], wb, gk)
+            gk = C.bf16(gx * (acts[k] > 0))
 
 
 def test_batch_index_selects_samples():
@@ -282,13 +333,16 @@ def test_fused_inference_equals_layer_kernels(B, H, W):
     net.set_fused(False)
     y_layer = net.forward(xd)
     assert torch.equal(y_fused, y_layer)
-    ys, _ = C.forward_stored(params, standardise(x, NORM[0], NORM[1]))
-    ys = ys.transpose(0, 3, 1, 2)
+    ys, acts = C.forward_stored(params, standardise(x, NORM[0], NORM[1]))
+    s3 = C.conv3x3(np.abs(acts[2]), np.abs(C.bf16(params[2][0])), np.abs(params[2][1]))
+    std = NORM[3][None, :, None, None].astype(np.float64)
+    mean = NORM[2][None, :, None, None].astype(np.float64)
     for clip in (0.5, 2.0):
         net.set_output_clip(clip)
         for fused in (True, False):
             net.set_fused(fused)
             y = net.forward(xd).cpu().numpy().astype(np.float64)
-            want = np.clip(ys, -clip, clip) * NORM[3][None, :, None, None] + NORM[2][None, :, None, None]
-            err = np.abs(y - want).max(axis=(0, 2, 3)) / NORM[3]
-            assert (err < 2e-2 * clip).all(), (clip, fused, err)
+            y_std = ((y - mean) / std).transpose(0, 2, 3, 1)
+            assert np.abs(y_std).max() <= clip * (1 + 2 ** -20)
+            check_elementwise(y_std, np.clip(ys, -clip, clip), s3,
+                              f"clip {clip} fused {fused} {B}x{H}x{W}")

@@ -333,3 +333,54 @@ def test_acoustic_pulse_reference_closed_form_checks():
     rr = np.linspace(0, 200, 4001)
     integral = np.trapezoid(2 * np.pi * rr * pulse_pressure(rr, 60.0, c, alpha), rr)
     assert integral == pytest.approx(np.pi / alpha, rel=1e-3)
+
+
+def test_paper_shock_tube_3to1():
+    """The shock tube of Sec. 5.2: (3 rho, 0, 3 p) | (rho, 0, p) at one
+    temperature, 401 x 2 points over 1 m, mu = 1e-5 kg/(m s) (3.03e-6 in
+    lattice units), sigma 0.4, T_r = 1460 K, extrapolated ends.  The paper
+    plots the profiles at an unstated time; here 400 steps (0.89 ms), before
+    any wave reaches an end.  Against the exact Riemann solution: pressure
+    and velocity of the star region within 1 %, shock within 2 cells of its
+    exact position.  Between the contact and the shock the temperature is
+    slightly low, as the paper reports and attributes to the non-conservative
+    entropy equation: the oracle's deficit there is about 0.5 %, asserted to
+    be a deficit (below the exact value) of less than 2 %."""
+    nx, ny, steps = 401, 2, 400
+    r, u, v, t = hi.paper_shock_tube(nx, ny)
+    mu = hi.paper_tube_mu(nx)
+    assert mu == pytest.approx(3.0324e-6, rel=1e-4)
+    S = oracle.OracleSolver(oracle.OracleParams(nx, ny, mu=mu, sigma=0.4, phi_mode="fd",
+                                                bc_x="extrapolate"), r, u, v, theta=t)
+    S.step(steps)
+    m = S.moments()
+    assert np.isfinite(m["rho"]).all()
+    p_inf = CS2 * t[0, 0]
+    L, R_ = (3.0, 0.0, 3.0 * p_inf), (1.0, 0.0, p_inf)
+    gamma = 1.4
+    pstar, ustar = riemann_exact.star_state(L, R_, gamma)
+    head, contact, shock = riemann_exact.wave_speeds(L, R_, gamma)
+    # the split lies half-way between nodes 199 and 200
+    xi = (np.arange(nx) - 199.5) / steps
+    rho = m["rho"].mean(0)
+    p = (m["rho"] * CS2 * m["theta"]).mean(0)
+    ux = m["ux"].mean(0)
+    th = m["theta"].mean(0)
+    # the star region between the rarefaction tail and the shock
+    rho_l, u_l, p_l = riemann_exact.sample(L, R_, gamma, np.array([0.5 * contact]))
+    tail = ustar - math.sqrt(gamma * pstar / rho_l[0])
+    star = (xi > tail + 0.2 * (contact - tail)) & (xi < shock - 0.2 * (shock - contact))
+    assert np.median(p[star]) == pytest.approx(pstar, rel=0.01)
+    assert np.median(ux[star]) == pytest.approx(ustar, rel=0.01)
+    # shock position: last node above the mid density of the jump
+    rs, _, _ = riemann_exact.sample(L, R_, gamma, np.array([0.5 * (contact + shock)]))
+    mid = 0.5 * (rs[0] + 1.0)
+    x_shock = np.where(rho > mid)[0].max() + 0.5 - 199.5
+    assert x_shock == pytest.approx(shock * steps, abs=2.0)
+    # temperature between contact and shock
+    band = (xi > contact + 0.2 * (shock - contact)) & (xi < shock - 0.2 * (shock - contact))
+    t_exact = pstar / (rs[0] * CS2)   # theta = p / (rho c_s^2)
+    deficit = float(np.median(th[band]) / t_exact - 1.0)
+    print(f"paper shock tube: p*/exact {np.median(p[star]) / pstar:.4f}, "
+          f"u*/exact {np.median(ux[star]) / ustar:.4f}, T deficit {deficit:+.4f}")
+    assert -0.02 < deficit < 0.0
