@@ -19,7 +19,7 @@ sound (the Ma 0 pulse moves at 1e-4 of c, and FP64 rounding of the
 populations, O(1e-16) of them per step, sets the floor of its velocity
 error).  Where a run amplifies rounding (under-resolved shocks, long
 supersonic runs), the bound is the larger of 1e-12 and ten times the
-oracle's own response to a 1e-15 relative density perturbation."""
+oracle's own response to one FP64 rounding of every stored value per step."""
 import numpy as np
 import pytest
 
@@ -157,17 +157,31 @@ def test_table1_original_model_parity_before_divergence():
 
 
 # ------------------------------------------------------------- shock tubes
-def _sensitivity_bound(nx, ny, fields, steps, mo, **kw):
-    """The oracle's own response to a 1e-15 relative density perturbation
-    (one value per column) after `steps` steps, per field, max-norm relative."""
+def _rounding_response(nx, ny, fields, steps, per_column=False, seed=0, **kw):
+    """The oracle's response to rounding: the same run with every stored
+    value (populations and entropy) multiplied by 1 + 2^-53 xi, xi ~ U[-1,
+    1), after every step -- one FP64 rounding's worth of difference per step,
+    as two correct implementations that order their sums differently would
+    accumulate.  In quasi-1D runs xi is drawn per column, so the run stays
+    one-dimensional as it does under the GPU's row-identical arithmetic.
+    Returns the unperturbed moments and the parity errors of the perturbed
+    run against them."""
     r, u, v, t = fields
-    s = oracle.entropy_from_theta(r, t, 1.4)
-    noise = np.random.default_rng(0).uniform(-1, 1, (1, nx)).repeat(ny, 0)
+    s = oracle.entropy_from_theta(r, t, kw.get("gamma", 1.4))
     okw = {k: kw[k] for k in OKEYS if k in kw}
-    B = oracle.OracleSolver(oracle.OracleParams(nx, ny, **okw), r * (1 + 1e-15 * noise), u, v,
-                            s=s)
-    B.step(steps)
-    return parity_errors(mo, B.moments())
+    A = oracle.OracleSolver(oracle.OracleParams(nx, ny, **okw), r, u, v, s=s)
+    B = oracle.OracleSolver(oracle.OracleParams(nx, ny, **okw), r, u, v, s=s)
+    A.step(steps)
+    rng = np.random.default_rng(seed)
+    for _ in range(steps):
+        B.step(1)
+        F, sv = B.state()
+        shp_f = (9, 1, nx) if per_column else F.shape
+        shp_s = (1, nx) if per_column else sv.shape
+        B.set_state(F * (1 + 2.0 ** -53 * rng.uniform(-1, 1, shp_f)),
+                    sv * (1 + 2.0 ** -53 * rng.uniform(-1, 1, shp_s)))
+    mo = A.moments()
+    return mo, B.moments()
 
 
 def test_paper_shock_tube_full_run():
@@ -177,17 +191,18 @@ def test_paper_shock_tube_full_run():
     O, G = pair(nx, ny, f, steps, **kw)
     mo, mg = O.moments(), gpu_moments(G)
     errs = parity_errors(mo, mg)
-    sens = _sensitivity_bound(nx, ny, f, steps, mo, **kw)
-    print("paper shock tube: gpu-oracle", errs, "oracle 1e-15 sensitivity", sens)
+    ref, pert = _rounding_response(nx, ny, f, steps, per_column=True, **kw)
+    sens = parity_errors(ref, pert)
+    print("paper shock tube: gpu-oracle", errs, "oracle rounding response", sens)
     for k in FIELDS:
         assert errs[k] <= max(1e-12, 10 * sens[k]), (k, errs[k], sens[k])
 
 
 def test_mach2_shock_strip_2000_steps():
     """The Mach-2 normal shock (C2b recipe, x extrapolated, seeded per-column
-    upstream perturbation) at 2048 x 4 over 2000 steps; like the Sod tube,
-    the under-resolved shock amplifies rounding, so the bound is the larger
-    of 1e-12 and ten times the oracle's own 1e-15 sensitivity."""
+    upstream perturbation) at 2048 x 4 over 2000 steps; the under-resolved
+    shock amplifies rounding, so the bound is the larger of 1e-12 and ten
+    times the oracle's response to per-step rounding."""
     nx, ny, steps = 2048, 4, 2000
     f = hi.normal_shock(nx, ny, mach=2.0, theta1=0.1, perturb=1e-3, seed=0)
     r_full = hi.normal_shock(nx, 512, mach=2.0, theta1=0.1, perturb=1e-3, seed=0)
@@ -203,8 +218,9 @@ def test_mach2_shock_strip_2000_steps():
             done = upto
         mo, mg = O.moments(), gpu_moments(G)
         errs = parity_errors(mo, mg)
-        sens = _sensitivity_bound(nx, ny, f, upto, mo, **kw)
-        print(f"mach 2 strip {upto} steps: gpu-oracle", errs, "oracle 1e-15 sensitivity", sens)
+        ref, pert = _rounding_response(nx, ny, f, upto, per_column=True, **kw)
+        sens = parity_errors(ref, pert)
+        print(f"mach 2 strip {upto} steps: gpu-oracle", errs, "oracle rounding response", sens)
         for k in ("rho", "ux", "s"):
             assert errs[k] <= max(1e-12, 10 * sens[k]), (upto, k, errs[k], sens[k])
 
@@ -215,7 +231,8 @@ def test_acoustic_pulses_match_oracle():
     domains, graph-replayed) against the oracle run on each: fields within
     1e-12 of their magnitude, and the pressure perturbation p - p_inf (1e-4
     of p, so a 1e-16 rounding of p is 1e-12 of it) within the larger of 1e-9
-    of its amplitude and ten times the oracle's own 1e-15 sensitivity."""
+    of its amplitude and ten times the oracle's response to per-step
+    rounding."""
     res = studies.acoustic_pulse()
     steps, cases = studies.acoustic_pulse_cases()
     n = 201
@@ -230,12 +247,8 @@ def test_acoustic_pulses_match_oracle():
         assert_parity(mo, g["fields"], what=f"pulse Ma {cs['mach']}")
         po = mo["rho"] * hi.CS2 * mo["theta"] - cs["p_inf"]
         err = np.abs(g["p_prime"] - po).max() / np.abs(po).max()
-        noise = np.random.default_rng(0).uniform(-1, 1, (n, n))
-        B = oracle.OracleSolver(oracle.OracleParams(n, n, **okw), r * (1 + 1e-15 * noise), u, v,
-                                theta=t)
-        B.step(steps)
-        mb = B.moments()
+        _, mb = _rounding_response(n, n, (r, u, v, t), steps, **cs["kw"])
         sens = np.abs(mb["rho"] * hi.CS2 * mb["theta"] - cs["p_inf"] - po).max() / np.abs(po).max()
         print(f"pulse Ma {cs['mach']}: p' error {err:.2e} of its amplitude, "
-              f"oracle 1e-15 sensitivity {sens:.2e}")
+              f"oracle rounding response {sens:.2e}")
         assert err <= max(1e-9, 10 * sens)
