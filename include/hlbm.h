@@ -196,6 +196,24 @@ void hlbm_destroy(hlbm_handle *h);
 /* Static message for a status code. */
 const char *hlbm_strerror(int code);
 
+/* For callers that cannot allocate device memory (no workspace, no handle,
+ * e.g. under graph capture or in loops that must not call hipMalloc): the
+ * conservation totals of hlbm_totals, computed from a raw state buffer
+ * instead of a handle.  p: the domain's parameters (validated as by
+ * hlbm_validate); state: device buffer of hlbm_state_bytes(p) bytes in the
+ * storage format of hlbm_save_state (read only); host_out4 as in
+ * hlbm_totals, with the same fixed-order FP64 reduction, so the same state
+ * gives the same bits.  The reduction partials (1024 x 6 doubles, 48 KiB)
+ * live in a fixed array of the library's own device memory, one per GPU,
+ * held until the process ends; the call allocates nothing.  Every call on
+ * one GPU shares that array: calls that overlap in time on one GPU (other
+ * streams or host threads) race and must be serialised by the caller.  No
+ * size limit beyond hlbm_validate's (the partial count does not depend on
+ * the grid).  Synchronises `stream`.  HLBM_OK, HLBM_EINVAL (invalid
+ * parameters or NULL pointer) or HLBM_EHIP. */
+int hlbm_state_totals(const hlbm_params *p, const void *state, double *host_out4,
+                      hlbm_stream_t stream);
+
 /* Entropy from temperature, s = c_v ln(theta / rho^(gamma-1)) with
  * c_v = c_s^2 / (gamma - 1) (Sec. 2.1, 2.4), over n device elements of
  * `dtype`.  Asynchronous. */

@@ -74,6 +74,7 @@ def lib():
             "hlbm_destroy": (None, [vp]),
             "hlbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "hlbm_entropy_from_theta": (ctypes.c_int, [i32, ctypes.c_double, vp, vp, vp, i64, vp]),
+            "hlbm_state_totals": (ctypes.c_int, [PP, vp, dp, vp]),
             "hlbm_batch_workspace_bytes": (sz, [PP, i32]),
             "hlbm_batch_init": (ctypes.c_int, [ctypes.POINTER(vp), PP, i32, vp, sz, vp, vp, vp, vp,
                                                vp]),
@@ -263,6 +264,18 @@ def entropy_from_theta(rho, theta, gamma, dtype="f64", device="cuda"):
                                          _ptr(th), _ptr(s), r.numel(), _stream()),
            "hlbm_entropy_from_theta")
     return s
+
+
+def state_totals(p: Params, state, stream=None):
+    """hlbm_state_totals: conservation totals of a raw state buffer (a
+    device uint8 tensor of hlbm_state_bytes(p) bytes, e.g. from
+    Solver.save_state), with the library's static scratch (no allocation)."""
+    cp = p.c()
+    _dev_buf(state, state.device, lib().hlbm_state_bytes(ctypes.byref(cp)), what="state")
+    out = (ctypes.c_double * 4)()
+    _check(lib().hlbm_state_totals(ctypes.byref(cp), _ptr(state), out, _stream(stream)),
+           "hlbm_state_totals")
+    return np.array(out[:])
 
 
 class Solver:

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -364,6 +365,64 @@ int hlbm_entropy_from_theta(int32_t dtype, double gamma, const void *rho, const 
   hipError_t e = dtype == HLBM_F64 ? hlbm::f64::entropy(rho, theta, s, n, gamma, st)
                                    : hlbm::f32::entropy(rho, theta, s, n, gamma, st);
   return hip_status(e);
+}
+
+}  // extern "C"
+
+// ======================================================================
+// Totals of a raw state buffer with library-owned scratch (no allocation)
+// ======================================================================
+// Reduction partials and result of hlbm_state_totals: a fixed-size array in
+// device memory, one copy per GPU, held until the process ends.  In host
+// code this name is only a handle for hipGetSymbolAddress; kernels receive
+// the device address that call returns.
+constexpr int kScratchDoubles = hlbm::kReduceParts * hlbm::kReduceVals + 32;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+double *scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current); nullptr if the lookup fails.
+double *device_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    scratch_ptr[dev] = (double *)ptr;
+  }
+  return scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int hlbm_state_totals(const hlbm_params *p, const void *state, double *host_out4,
+                      hlbm_stream_t stream) {
+  if (hlbm_validate(p) != HLBM_OK || !state || !host_out4) return HLBM_EINVAL;
+  double *ws = device_scratch();
+  if (!ws) return HLBM_EHIP;
+  hlbm::HostDomain dom;
+  fill_domain(p, &dom);
+  hipStream_t st = (hipStream_t)stream;
+  double *parts = ws;
+  double *out = ws + hlbm::kReduceParts * hlbm::kReduceVals;
+  hipError_t e = p->dtype == HLBM_F64
+                     ? hlbm::f64::reduce(dom, state, parts, hlbm::kReduceParts, out, st)
+                     : hlbm::f32::reduce(dom, state, parts, hlbm::kReduceParts, out, st);
+  double host[hlbm::kReduceVals];
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host, out, sizeof(double) * hlbm::kReduceVals, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return HLBM_EHIP;
+  for (int k = 0; k < 4; ++k) host_out4[k] = host[k];
+  return HLBM_OK;
 }
 
 }  // extern "C"
