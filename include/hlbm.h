@@ -104,6 +104,15 @@ typedef struct {
                            in the original model the paper compares against
                            (Sec. 2.3, Table 1); with e1_centred = e2_off = 1
                            this is that model */
+  int32_t steps_per_launch; /* 0: automatic (2 for FP32 domains periodic along both
+                           axes, else 1); 1: one step per kernel launch; 2: two
+                           steps per launch, reading the state once and writing
+                           it once every two steps (periodic along both axes
+                           only, HLBM_EINVAL otherwise).  The per-node
+                           arithmetic is the same either way (FP64 results
+                           agree bitwise); hlbm_step runs an odd last step
+                           alone.  tile_w / tile_h then apply to the two-step
+                           sweep (tile_w 64 or 128 in FP64) */
 } hlbm_params;
 
 typedef struct hlbm_handle hlbm_handle;
@@ -124,14 +133,26 @@ size_t hlbm_state_bytes(const hlbm_params *p);
 /* Check parameters without touching the GPU: HLBM_OK or HLBM_EINVAL. */
 int hlbm_validate(const hlbm_params *p);
 
-/* Tile shape hlbm_step launches for these parameters: tile_w / tile_h as
- * given, or the defaults when they are 0 (192-column tiles from 1024 columns,
- * 128 below, 64 for nx <= 64; 16-row strips at 192 columns in FP32, 32
- * otherwise, halved down to 4 rows until about 768 workgroups exist in FP32
- * or 512 in FP64; never more rows than ny).  Writes *host_tile_w and
- * *host_tile_h; HLBM_OK, or HLBM_EINVAL if the parameters are invalid or a
- * pointer is NULL.  Host-only; callable without a GPU. */
+/* Tile shape of hlbm_step's launches for these parameters (of the two-step
+ * sweep when hlbm_launch_plan reports two steps per launch): tile_w / tile_h
+ * as given, or the defaults when they are 0.  One step per launch:
+ * 192-column tiles from 1024 columns, 128 below, 64 for nx <= 64; 16-row
+ * strips at 192 columns in FP32, 32 otherwise, halved down to 4 rows until
+ * about 768 workgroups exist in FP32 or 512 in FP64; never more rows than
+ * ny.  Writes *host_tile_w and *host_tile_h; HLBM_OK, or HLBM_EINVAL if the
+ * parameters are invalid or a pointer is NULL.  Host-only; callable without
+ * a GPU. */
 int hlbm_launch_shape(const hlbm_params *p, int32_t *host_tile_w, int32_t *host_tile_h);
+
+/* Launch plan of hlbm_step for these parameters: steps per kernel launch (1
+ * or 2, see steps_per_launch) and the tile shape of that launch (for two
+ * steps per launch: tile_w / tile_h as given, or 192-column tiles from 1024
+ * columns in FP32, 128 otherwise, 64 for nx <= 64, with 64-row strips halved
+ * down to 8 rows until about 384 workgroups exist).  HLBM_OK, or
+ * HLBM_EINVAL if the parameters are invalid or a pointer is NULL.
+ * Host-only. */
+int hlbm_launch_plan(const hlbm_params *p, int32_t *host_steps_per_launch, int32_t *host_tile_w,
+                     int32_t *host_tile_h);
 
 /* Initialise a domain from macroscopic fields (algorithm of Sec. 3.5, steps
  * 1-4): F0 = f^eq + f^1[a1FD] - psi/2 at every node, so the first step sees
@@ -147,7 +168,8 @@ int hlbm_init(hlbm_handle **out, const hlbm_params *p, void *workspace, size_t w
               const void *rho, const void *ux, const void *uy, const void *s,
               hlbm_stream_t stream);
 
-/* Enqueue nsteps (>= 0) time steps (Sec. 3.5, steps 5-11).  Asynchronous.
+/* Enqueue nsteps (>= 0) time steps (Sec. 3.5, steps 5-11), one or two per
+ * kernel launch as hlbm_launch_plan reports.  Asynchronous.
  * With bc_y = HLBM_BC_WALL every step (and hlbm_init) ends by rebuilding the
  * two wall rows, a regularised wet-node wall (our reading of the wall
  * condition of the thermal Couette case, Sec. 4.4, which the paper cites

@@ -39,7 +39,8 @@ class CParams(ctypes.Structure):
                 ("rho_ref", ctypes.c_double), ("theta_ref", ctypes.c_double),
                 ("sgn_eps", ctypes.c_double), ("wall_ux_lo", ctypes.c_double),
                 ("wall_ux_hi", ctypes.c_double), ("wall_theta", ctypes.c_double),
-                ("precise_theta", ctypes.c_int32), ("feq_order", ctypes.c_int32)]
+                ("precise_theta", ctypes.c_int32), ("feq_order", ctypes.c_int32),
+                ("steps_per_launch", ctypes.c_int32)]
 
 
 _lib = None
@@ -60,6 +61,8 @@ def lib():
             "hlbm_workspace_bytes": (sz, [PP]),
             "hlbm_state_bytes": (sz, [PP]),
             "hlbm_launch_shape": (ctypes.c_int, [PP, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+            "hlbm_launch_plan": (ctypes.c_int, [PP, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                                ctypes.POINTER(i32)]),
             "hlbm_validate": (ctypes.c_int, [PP]),
             "hlbm_init": (ctypes.c_int, [ctypes.POINTER(vp), PP, vp, sz, vp, vp, vp, vp, vp]),
             "hlbm_step": (ctypes.c_int, [vp, i32, vp]),
@@ -162,6 +165,9 @@ class Params:
     # 4: fourth-order Hermite expansion (present model); 3: truncated at third
     # order (the original model, with e1_centred and e2_off)
     feq_order: int = 4
+    # 0: automatic (two steps per kernel launch for FP32 domains periodic in
+    # both axes), 1 or 2 steps per launch
+    steps_per_launch: int = 0
 
     def c(self) -> CParams:
         return CParams(self.nx, self.ny, BC[self.bc_x], BC[self.bc_y],
@@ -169,7 +175,7 @@ class Params:
                        int(self.e1_centred), int(self.e2_off), int(self.tile_w), int(self.tile_h),
                        self.gamma, self.prandtl, self.mu, self.sigma, self.rho_ref, self.theta_ref,
                        self.sgn_eps, self.wall_ux_lo, self.wall_ux_hi, self.wall_theta,
-                       int(self.precise_theta), int(self.feq_order))
+                       int(self.precise_theta), int(self.feq_order), int(self.steps_per_launch))
 
     @property
     def torch_dtype(self):
@@ -194,6 +200,15 @@ def launch_shape(p: Params):
     _check(lib().hlbm_launch_shape(ctypes.byref(cp), ctypes.byref(w), ctypes.byref(h)),
            "hlbm_launch_shape")
     return int(w.value), int(h.value)
+
+
+def launch_plan(p: Params):
+    """(steps_per_launch, tile_w, tile_h) of hlbm_step for p."""
+    cp = p.c()
+    n, w, h = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().hlbm_launch_plan(ctypes.byref(cp), ctypes.byref(n), ctypes.byref(w),
+                                  ctypes.byref(h)), "hlbm_launch_plan")
+    return int(n.value), int(w.value), int(h.value)
 
 
 def _stream(stream=None):

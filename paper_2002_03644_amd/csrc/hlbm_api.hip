@@ -57,7 +57,9 @@ bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 struct hlbm_handle {
   hlbm_params p;
   hlbm::HostDomain dom;
-  hlbm::TileShape tile;
+  hlbm::TileShape tile;   // one step per launch
+  hlbm::TileShape tile2;  // two steps per launch
+  int spl;                // steps per launch (1 or 2)
   Layout L;
   char *ws;
   int cur;
@@ -88,8 +90,22 @@ void rest_equilibrium(double rho, double theta, int order, double f[9]) {
   f[5] = f[6] = f[7] = f[8] = bd / 36.0;
 }
 
+// Steps per launch: two-step sweeps need periodic axes (validated), and are
+// the default for FP32 there; FP64's two-level sweep holds one wave per SIMD.
+int steps_per_launch(const hlbm_params *p) {
+  if (p->steps_per_launch) return p->steps_per_launch;
+  const bool periodic = p->bc_x == HLBM_BC_PERIODIC && p->bc_y == HLBM_BC_PERIODIC;
+  return periodic && p->dtype == HLBM_F32 ? 2 : 1;
+}
+
 hlbm::TileShape default_tile(const hlbm_params *p) {
+  if (steps_per_launch(p) == 2)  // tile_w / tile_h belong to the two-step sweep
+    return hlbm::step_tile(p->nx, p->ny, 0, 0, (int)elem_size(p->dtype));
   return hlbm::step_tile(p->nx, p->ny, p->tile_w, p->tile_h, (int)elem_size(p->dtype));
+}
+
+hlbm::TileShape default_tile2(const hlbm_params *p) {
+  return hlbm::step2_tile(p->nx, p->ny, p->tile_w, p->tile_h, (int)elem_size(p->dtype));
 }
 
 void fill_domain(const hlbm_params *p, hlbm::HostDomain *d) {
@@ -180,6 +196,11 @@ int hlbm_validate(const hlbm_params *p) {
   if (p->e1_centred < 0 || p->e1_centred > 1 || p->e2_off < 0 || p->e2_off > 1) return HLBM_EINVAL;
   if (p->precise_theta < 0 || p->precise_theta > 1) return HLBM_EINVAL;
   if (p->feq_order != 0 && p->feq_order != 3 && p->feq_order != 4) return HLBM_EINVAL;
+  if (p->steps_per_launch < 0 || p->steps_per_launch > 2) return HLBM_EINVAL;
+  if (p->steps_per_launch == 2 &&
+      (p->bc_x != HLBM_BC_PERIODIC || p->bc_y != HLBM_BC_PERIODIC ||
+       (p->dtype == HLBM_F64 && p->tile_w != 0 && p->tile_w > 128)))
+    return HLBM_EINVAL;
   if (p->tile_w != 0 && p->tile_w != 64 && p->tile_w != 128 && p->tile_w != 192 &&
       p->tile_w != 256)
     return HLBM_EINVAL;
@@ -196,7 +217,19 @@ int hlbm_validate(const hlbm_params *p) {
 
 int hlbm_launch_shape(const hlbm_params *p, int32_t *host_tile_w, int32_t *host_tile_h) {
   if (!host_tile_w || !host_tile_h || hlbm_validate(p) != HLBM_OK) return HLBM_EINVAL;
-  const hlbm::TileShape t = default_tile(p);
+  const hlbm::TileShape t = steps_per_launch(p) == 2 ? default_tile2(p) : default_tile(p);
+  *host_tile_w = t.bw;
+  *host_tile_h = t.rows;
+  return HLBM_OK;
+}
+
+int hlbm_launch_plan(const hlbm_params *p, int32_t *host_steps_per_launch, int32_t *host_tile_w,
+                     int32_t *host_tile_h) {
+  if (!host_steps_per_launch || !host_tile_w || !host_tile_h || hlbm_validate(p) != HLBM_OK)
+    return HLBM_EINVAL;
+  const int spl = steps_per_launch(p);
+  const hlbm::TileShape t = spl == 2 ? default_tile2(p) : default_tile(p);
+  *host_steps_per_launch = spl;
   *host_tile_w = t.bw;
   *host_tile_h = t.rows;
   return HLBM_OK;
@@ -231,6 +264,8 @@ int hlbm_init(hlbm_handle **out, const hlbm_params *p, void *workspace, size_t w
   h->cur = 0;
   h->steps = 0;
   h->tile = default_tile(p);
+  h->tile2 = default_tile2(p);
+  h->spl = steps_per_launch(p);
   fill_domain(p, &h->dom);
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
@@ -260,7 +295,21 @@ int hlbm_init(hlbm_handle **out, const hlbm_params *p, void *workspace, size_t w
 int hlbm_step(hlbm_handle *h, int32_t nsteps, hlbm_stream_t stream) {
   if (!h || nsteps < 0) return HLBM_EINVAL;
   hipStream_t st = (hipStream_t)stream;
-  for (int32_t n = 0; n < nsteps; ++n) {
+  int32_t n = 0;
+  if (h->spl == 2) {  // periodic domains, no walls
+    for (; n + 2 <= nsteps; n += 2) {
+      hipError_t e =
+          h->p.dtype == HLBM_F64
+              ? hlbm::f64::step2(h->dom, buf(h, h->cur), buf(h, h->cur ^ 1), status_word(h),
+                                 h->tile2, st)
+              : hlbm::f32::step2(h->dom, buf(h, h->cur), buf(h, h->cur ^ 1), status_word(h),
+                                 h->tile2, st);
+      if (e != hipSuccess) return HLBM_EHIP;
+      h->cur ^= 1;
+      h->steps += 2;
+    }
+  }
+  for (; n < nsteps; ++n) {
     hipError_t e;
     if (h->p.dtype == HLBM_F64)
       e = hlbm::f64::step(h->dom, buf(h, h->cur), buf(h, h->cur ^ 1), status_word(h), h->tile, st);

@@ -605,6 +605,14 @@ __global__ __launch_bounds__(CW + 64) void k_step_batch(BatchArgs a) {
   }
 }
 
+}  // namespace HLBM_NS
+}  // namespace hlbm
+
+#include "hlbm_step2.hpp"
+
+namespace hlbm {
+namespace HLBM_NS {
+
 // ------------------------------------------------------ initialisation
 //
 // F0 = f^eq + f^1[a1FD] - psi/2 (algorithm of Sec. 3.5, steps 2-4), one

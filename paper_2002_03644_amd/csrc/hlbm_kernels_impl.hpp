@@ -72,6 +72,39 @@ hipError_t step(const HostDomain &h, const void *src, void *dst, unsigned *statu
   return hipGetLastError();
 }
 
+hipError_t step2(const HostDomain &h, const void *src, void *dst, unsigned *status,
+                 const TileShape &tile, hipStream_t st) {
+  StepArgs a;
+  a.d = to_device(h);
+  a.src = (const real *)src;
+  a.dst = (real *)dst;
+  a.status = status;
+  a.rows = tile.rows;
+  a.nbx = (h.nx + tile.bw - 1) / tile.bw;
+  a.nby = (h.ny + tile.rows - 1) / tile.rows;
+  a.xcd_remap = tile.xcd_remap;
+  const int nblk = a.nbx * a.nby;
+  switch (tile.bw) {
+  case 64:
+    hipLaunchKernelGGL(k_step2<64>, dim3(nblk), dim3(64 + 64), 0, st, a);
+    break;
+  case 128:
+    hipLaunchKernelGGL(k_step2<128>, dim3(nblk), dim3(128 + 64), 0, st, a);
+    break;
+  case 192:
+    if (sizeof(real) != 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_step2<192>, dim3(nblk), dim3(192 + 64), 0, st, a);
+    break;
+  case 256:
+    if (sizeof(real) != 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_step2<256>, dim3(nblk), dim3(256 + 64), 0, st, a);
+    break;
+  default:
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t wall(const HostDomain &h, void *state, hipStream_t st) {
   WallArgs a;
   a.d = to_device(h);

@@ -55,6 +55,29 @@ inline TileShape step_tile(int nx, int ny, int tile_w, int tile_h, int elem_size
   return t;
 }
 
+// Tile shape of the two-step sweep (periodic domains).  Its workgroup reads a
+// radius-4 halo, rows + 8 rows for `rows` output rows, so it takes taller
+// strips than the one-step sweep: at 8192^2 FP32 (ms per step) 192 x 16
+// 1.023, x 32 0.911, x 48 0.891, x 64 0.888, x 96 0.906; 128 x 32 0.924,
+// x 64 0.892; 256 x 64 1.736 (two workgroups per CU in LDS).  Small grids
+// halve the strips down to 8 rows until about 384 workgroups exist (the
+// sweep holds three workgroups per CU at 192 columns in FP32).  FP64 keeps
+// 128-column tiles, whose two levels of rings fit the LDS of one workgroup.
+inline TileShape step2_tile(int nx, int ny, int tile_w, int tile_h, int elem_size) {
+  TileShape t;
+  t.bw = tile_w ? tile_w
+                : (nx <= 64 ? 64 : (nx >= 1024 && elem_size == 4 ? 192 : 128));
+  int rows = tile_h ? tile_h : 64;
+  if (!tile_h) {
+    const long long nbx = (nx + t.bw - 1) / t.bw;
+    while (rows > 8 && nbx * ((ny + rows - 1) / rows) < 384) rows /= 2;
+  }
+  if (rows > ny) rows = ny;
+  t.rows = rows;
+  t.xcd_remap = 1;
+  return t;
+}
+
 // Elements from one state row to the next: nx rounded up to 64, so that every
 // row, and with it every tile's row segment, starts 256-byte aligned (FP32).
 // Rows of other widths lost 5 % (6000 and 14000 columns, rows 64-byte
@@ -85,6 +108,8 @@ inline long long plane_stride(int nx, int ny, int elem_size) {
   namespace NS {                                                                            \
   hipError_t step(const HostDomain &d, const void *src, void *dst, unsigned *status,        \
                   const TileShape &tile, hipStream_t st);                                   \
+  hipError_t step2(const HostDomain &d, const void *src, void *dst, unsigned *status,       \
+                   const TileShape &tile, hipStream_t st);                                  \
   hipError_t init(const HostDomain &d, const void *rho, const void *ux, const void *uy,     \
                   const void *s, void *dst, hipStream_t st);                                \
   hipError_t wall(const HostDomain &d, void *state, hipStream_t st);                        \

@@ -81,6 +81,23 @@ def test_validate_feq_order(order, ok):
     assert validate(_params(feq_order=order)) == (HLBM_OK if ok else HLBM_EINVAL)
 
 
+def test_launch_plan_and_steps_per_launch():
+    from paper_2002_03644_amd import HLBM_EINVAL, launch_plan, validate
+    assert launch_plan(_params(nx=8192, ny=8192))[0] == 2               # FP32 periodic
+    assert launch_plan(_params(nx=8192, ny=8192, dtype="f64"))[0] == 1  # FP64 default
+    assert launch_plan(_params(bc_x="extrapolate"))[0] == 1
+    assert launch_plan(_params(bc_y="wall", wall_theta=0.2))[0] == 1
+    assert launch_plan(_params(steps_per_launch=1))[0] == 1
+    spl, tw, th = launch_plan(_params(nx=8192, ny=8192))
+    assert (tw, th) == (192, 64)
+    assert launch_plan(_params(nx=100, ny=100, dtype="f64", steps_per_launch=2))[0] == 2
+    for bad in (dict(steps_per_launch=3), dict(steps_per_launch=-1),
+                dict(steps_per_launch=2, bc_x="extrapolate"),
+                dict(steps_per_launch=2, bc_y="wall", wall_theta=0.2),
+                dict(steps_per_launch=2, dtype="f64", tile_w=192)):
+        assert validate(_params(**bad)) == HLBM_EINVAL, bad
+
+
 def test_wall_parameters_validated_on_the_host():
     from paper_2002_03644_amd import HLBM_EINVAL, HLBM_OK, validate
     ok = dict(bc_y="wall", wall_theta=0.2, wall_ux_hi=0.1)
@@ -149,8 +166,22 @@ def test_large_planes_get_a_stride_off_the_power_of_two(dt, es):
     (300, 3, "f32", (128, 3)),
 ])
 def test_default_launch_shape(nx, ny, dt, shape):
+    """Defaults of the one-step sweep."""
     from paper_2002_03644_amd import launch_shape
-    assert launch_shape(_params(nx=nx, ny=ny, dtype=dt)) == shape
+    assert launch_shape(_params(nx=nx, ny=ny, dtype=dt, steps_per_launch=1)) == shape
+
+
+@pytest.mark.parametrize("nx,ny,dt,shape", [
+    (8192, 8192, "f32", (192, 64)),   # the bench grid
+    (1024, 1024, "f32", (192, 16)),   # halved until about 384 workgroups
+    (256, 256, "f32", (128, 8)),
+    (64, 64, "f32", (64, 8)),
+    (1, 1, "f32", (64, 1)),           # never more rows than ny
+    (1024, 1024, "f64", (128, 16)),   # FP64 keeps 128-column tiles
+])
+def test_default_two_step_shape(nx, ny, dt, shape):
+    from paper_2002_03644_amd import launch_plan
+    assert launch_plan(_params(nx=nx, ny=ny, dtype=dt, steps_per_launch=2)) == (2,) + shape
 
 
 def test_launch_shape_takes_given_tiles_and_rejects_bad_input():
