@@ -3,8 +3,10 @@
 Workload: decaying compressible turbulence on an 8192 x 8192 periodic grid
 (seeded random-phase solenoidal velocity, E(k) ~ k^4 exp(-2 (k/8)^2),
 turbulent Mach 0.5, rho = 1, theta = 240/1183), nu = 1e-3, sigma = 0, FP32
-storage.  One step = one launch of the fused step kernel over the whole grid
-(collision, correction term, streaming and entropy update).
+storage.  A step is the whole fused update of every node (collision,
+correction term, streaming and entropy update); on this periodic grid the
+library advances two steps per kernel launch (the two-step sweep reads the
+state once and writes it once per two steps).
 
 Prints ONE JSON line: MLUPS (million lattice updates per second), the HBM
 roofline of the step kernel, the FP64 CPU oracle timed on a bounded sample of
@@ -29,11 +31,14 @@ sys.path.insert(0, ROOT)
 METRIC = ("HLBM MLUPS & % HBM roofline @8192² FP32; learned-vs-plain time at equal L2 "
           "error")
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
-BYTES_PER_NODE = 80            # read 9 populations + s, write 9 + s, FP32
-# sources that decide the step kernel and its launch shape (tile defaults)
+BYTES_PER_NODE = 80            # per lattice update: read 9 populations + s, write 9 + s, FP32
+# sources that decide the step kernels and their launch shapes (tile defaults)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2002_03644_amd", "csrc", f)
-               for f in ("hlbm_device.hpp", "hlbm_launch.hpp")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_f32_turbulence8192_traffic.txt")
+               for f in ("hlbm_device.hpp", "hlbm_step2.hpp", "hlbm_launch.hpp")]
+# HBM counter summaries of the dominant kernel, per steps per launch
+TRAFFIC_FILES = {1: os.path.join(ROOT, "profiles", "k_step_f32_turbulence8192_traffic.txt"),
+                 2: os.path.join(ROOT, "profiles", "k_step2_f32_turbulence8192_traffic.txt")}
+KERNEL_NAMES = {1: "hlbm::f32::k_step<{w}>", 2: "hlbm::f32::k_step2<{w}>"}
 
 
 def kernel_hash() -> str:
@@ -44,12 +49,12 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(nodes: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary
-    (lines `key: value`), if it was taken on the current kernel source at
-    this grid size; else None."""
+def measured_traffic(nodes: int, spl: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    the kernel that does `spl` steps per launch (lines `key: value`), if it
+    was taken on the current kernel source at this grid size; else None."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(TRAFFIC_FILES[spl]) as fh:
             kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
     except OSError:
         return None
@@ -169,6 +174,8 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--tile-w", type=int, default=0)
     ap.add_argument("--tile-h", type=int, default=0)
+    ap.add_argument("--steps-per-launch", type=int, default=0, choices=[0, 1, 2],
+                    help="0: the library's plan (two steps per launch here), 1 or 2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true",
                     help="skip the FP64 run of the same workload (100 steps)")
@@ -206,18 +213,23 @@ def main():
     import torch
 
     import hlbm_inputs as hi
-    from paper_2002_03644_amd import Params, Solver, launch_shape
+    from paper_2002_03644_amd import Params, Solver, launch_plan
 
     n = args.n
     print(f"[bench] generating {n}x{n} turbulence", file=sys.stderr, flush=True)
     r, u, v, t = hi.turbulence(n, 0.5, hi.THETA_PAPER, seed=0)
     params = Params(n, n, dtype="f32", mu=1e-3, sigma=0.0, tile_w=args.tile_w,
-                    tile_h=args.tile_h)
+                    tile_h=args.tile_h, steps_per_launch=args.steps_per_launch)
+    spl, tile_w, tile_h = launch_plan(params)
     dev = torch.device("cuda:0")
     fields = [torch.from_numpy(a.astype(np.float32)).to(dev) for a in (r, u, v, t)]
     S = Solver(params, *fields[:3], theta=fields[3], device=dev)
     del fields
     torch.cuda.synchronize()
+    # The library copy of the step's bytes (the practical-bandwidth reference
+    # reported below) runs first: it also brings the memory clocks up after
+    # the host-side set-up, which short timed windows would otherwise include.
+    stream_ref = copy_reference(n, dev)
     print("[bench] warmup", file=sys.stderr, flush=True)
     S.step(args.warmup)
     torch.cuda.synchronize()
@@ -240,11 +252,20 @@ def main():
     print(f"[bench] {ms_per_step:.4f} ms/step, {mlups:.0f} MLUPS, wall {wall:.2f} s, "
           f"status {code}, max CFL {max_cfl:.3f}", file=sys.stderr, flush=True)
 
-    achieved = BYTES_PER_NODE * nodes / (ms_per_step / 1e3) / 1e9
-    traffic = measured_traffic(nodes)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+    # the dominant kernel does `spl` lattice updates of every node per
+    # launch; its algorithmic bytes per launch are 80 B x nodes x spl, and
+    # its average launch duration is the timed region over its launches
+    launches = args.steps // spl
+    bytes_per_launch = BYTES_PER_NODE * nodes * spl
+    ms_per_launch = ms_per_step * spl
+    achieved = bytes_per_launch / (ms_per_launch / 1e3) / 1e9
+    traffic = measured_traffic(nodes, spl) if args.steps % spl == 0 else None
+    roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[spl].format(w=tile_w),
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic}
+                "traffic": traffic, "steps_per_launch": spl, "launches": launches,
+                "algorithmic_bytes_per_launch": bytes_per_launch,
+                "ms_per_launch": round(ms_per_launch, 5)}
 
     if args.copy_calibration:
         # a plain elementwise copy kernel moving 2 GiB in and 2 GiB out, whose
@@ -257,7 +278,6 @@ def main():
 
     del S
     torch.cuda.empty_cache()
-    stream_ref = copy_reference(n, dev)
     stream_ref["step_frac_of_copy"] = round(achieved / stream_ref["achieved"], 4)
     f64 = None if args.no_f64 else f64_same_config(n, (r, u, v, t), args.tile_w, args.tile_h)
     del r, u, v, t
@@ -276,7 +296,7 @@ def main():
            "config": {"workload": f"decaying compressible turbulence {n}x{n} periodic, "
                                   "Ma_t 0.5, nu 1e-3, sigma 0, FP32 storage",
                       "nx": n, "ny": n, "global_batch": 1, "parallelism": "none",
-                      "tile_w": launch_shape(params)[0], "tile_h": launch_shape(params)[1],
+                      "steps_per_launch": spl, "tile_w": tile_w, "tile_h": tile_h,
                       "tiles_given": bool(params.tile_w and params.tile_h),
                       "status_after": int(code)},
            "roofline": roofline, "cpu_baseline": cpu, "stream_reference": stream_ref,
@@ -491,53 +511,123 @@ def bench_couette(args):
     print(json.dumps(out), flush=True)
 
 
+def batch_cpu_baseline(specs, params, fields, count=12, steps=10, seed=0):
+    """The FP64 oracle on a bounded sample of the batch: `count` domains
+    drawn at random (seeded) from the batch, `steps` steps each after one
+    warm-up step, on the host cores; MLUPS over the sample's node updates."""
+    import numpy as np
+
+    import oracle
+    rng = np.random.default_rng(seed)
+    pick = sorted(rng.choice(len(specs), size=count, replace=False).tolist())
+    nodes, secs = 0, 0.0
+    for k in pick:
+        p = params[k]
+        r, u, v, t = fields[k]
+        S = oracle.OracleSolver(oracle.OracleParams(p.nx, p.ny, mu=p.mu, sigma=p.sigma), r, u, v,
+                                theta=t)
+        S.step(1)
+        t0 = time.perf_counter()
+        S.step(steps)
+        secs += time.perf_counter() - t0
+        nodes += p.nx * p.ny * steps
+        del S
+    return {"value": round(nodes / secs / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"{count} domains of the batch (indices {pick}, "
+                      f"{sum(params[k].nx * params[k].ny for k in pick)} nodes), {steps} steps "
+                      f"each after 1 warm-up step, FP64, {secs:.1f} s"}
+
+
 def bench_batch(args):
     """256 independent periodic domains (sizes log-uniform 64..1016, vortex or
-    turbulence, Mach 0.1-2.0, seed 0), FP32, one persistent launch per step."""
+    turbulence, Mach 0.1-2.0, seed 0), FP32, graph-replayed persistent
+    launches.  Domains whose flow leaves the method's stability range
+    diverge and are frozen (their tiles are skipped); the value counts only
+    the lattice updates actually performed.  The step at which each domain
+    diverges is found in an untimed pass over the same steps (the run is
+    deterministic: the timed run is checked to flag the same domains), and a
+    domain counts its full steps inside the timed window; the step in which
+    it is flagged, partly done, is left out (upper bound reported beside)."""
+    import numpy as np
     import torch
 
     import hlbm_inputs as hi
     from paper_2002_03644_amd import BatchSolver, Params
     specs = hi.batch_specs(256, seed=0)
-    params = [Params(sp.n, sp.n, dtype="f32", mu=1e-3, sigma=0.0, theta_ref=sp.theta)
-              for sp in specs]
+    params = [Params(sp.n, sp.n, dtype="f32", mu=1e-3, sigma=0.0, theta_ref=sp.theta,
+                     steps_per_launch=args.steps_per_launch) for sp in specs]
     fields = [hi.batch_domain_fields(sp) for sp in specs]
     B = BatchSolver(params, fields)
-    del fields
     if args.tile_w and args.tile_h:
         B.set_tile(args.tile_w, args.tile_h)
         tw, th = args.tile_w, args.tile_h
     else:
         tw, th = B.autotune(steps=10)
-    B.step(args.warmup, graph=True)
+    sizes = np.array([p.nx * p.ny for p in params], dtype=np.int64)
+    W, K = args.warmup, args.steps
+    spl = B.plan()[0]
+    # untimed pass over the same sequence of launches as the timed run (the
+    # graphs replay the same kernels): spl-step launches, then one-step
+    # launches for a remainder, for the warm-up and then the timed steps.
+    # A domain flagged in the launch covering steps (a, b] did a steps in full.
+    seq = [spl] * (W // spl) + [1] * (W % spl) + [spl] * (K // spl) + [1] * (K % spl)
+    snap = B.save_state()
+    never = np.iinfo(np.int64).max
+    div = np.full(len(params), never, dtype=np.int64)   # steps done before the flagging launch
+    div_end = np.full(len(params), never, dtype=np.int64)
+    done_steps = 0
+    for n_l in seq:
+        B.step(n_l, graph=False)
+        _, flags = B.status()
+        new = (flags != 0) & (div == never)
+        div[new] = done_steps
+        div_end[new] = done_steps + n_l
+        done_steps += n_l
+    B.load_state(snap)          # same state, flags cleared
+    del snap
+    B.step(W, graph=True)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(B.stream)
-    B.step(args.steps, graph=True)
+    B.step(K, graph=True)
     e1.record(B.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     bad, flags = B.status()
-    active = sum(p.nx * p.ny for p, f in zip(params, flags) if not f)
-    mlups = active * args.steps / (ms / 1e3) / 1e6
+    expect = div != never
+    deterministic = bool(np.array_equal(flags != 0, expect))
+    # full steps of each domain inside the window (W, W + K]; the flagging
+    # launch (at most spl steps) is the partial part
+    full = np.clip(np.minimum(div, W + K) - W, 0, K)
+    partial = np.where(div != never,
+                       np.clip(np.minimum(div_end, W + K) - np.maximum(div, W), 0, K), 0)
+    done = int((sizes * full).sum())
+    upper = int((sizes * (full + partial)).sum())
+    mlups = done / (ms / 1e3) / 1e6
+    gbs = BYTES_PER_NODE * done / (ms / 1e3) / 1e9
+    cpu = None if args.no_cpu_baseline else batch_cpu_baseline(specs, params, fields)
     out = {"metric": "batched HLBM aggregate MLUPS (256 domains)", "value": round(mlups, 1),
-           "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(ms / args.steps, 5), "higher_is_better": True,
+           "unit": "MLUPS", "n_gpus": 1, "steps": K, "warmup": W,
+           "ms_per_step": round(ms / K, 5), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "256 periodic domains 64^2..1016^2 (seed 0), vortex or "
                                   "turbulence, Mach 0.1-2.0, FP32, hipGraph replay",
-                      "nodes_total": B.nodes, "nodes_active_at_end": active,
-                      # all domains over the timed steps, frozen ones included
-                      "all_nodes_mlups": round(B.nodes * args.steps / (ms / 1e3) / 1e6, 1),
-                      "domains_diverged": int(bad), "tile_w": tw, "tile_h": th},
-           "roofline": {"bound": "hbm",
-                        "achieved": round(BYTES_PER_NODE * active / (ms / args.steps / 1e3) / 1e9,
-                                          1),
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(BYTES_PER_NODE * active / (ms / args.steps / 1e3) / 1e9
-                                      / HBM_PEAK_GBS, 4), "traffic": None},
-           "cpu_baseline": None}
+                      "nodes_total": int(sizes.sum()),
+                      "node_updates_stated": int(sizes.sum()) * K,
+                      "node_updates_performed": done,
+                      "node_updates_upper_bound": upper,
+                      "upper_bound_mlups": round(upper / (ms / 1e3) / 1e6, 1),
+                      "domains_diverged_by_end": int(bad),
+                      "domains_active_whole_window": int((div == never).sum()),
+                      "divergence_steps_reproduced": deterministic,
+                      "steps_per_launch": spl, "tile_w": tw, "tile_h": th},
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "traffic": None,
+                        "algorithmic_bytes": "80 B per performed lattice update"},
+           "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 

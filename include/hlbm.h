@@ -266,11 +266,14 @@ int hlbm_batch_init(hlbm_batch **out, const hlbm_params *params, int32_t count, 
                     size_t ws_bytes, const void *rho, const void *ux, const void *uy,
                     const void *s, hlbm_stream_t stream);
 
-/* Enqueue nsteps steps of all domains.  use_graph = 1 (stream must not be
- * NULL) replays a captured sixteen-step hipGraph while sixteen or more steps
- * remain, then a two-step one, and runs an odd last step eagerly; each graph
- * is captured on first use and again after the state has moved to the other
- * buffer or the tile shape changed.  HLBM_EHIP if a capture or launch fails. */
+/* Enqueue nsteps steps of all domains.  When every domain's own plan is two
+ * steps per launch (FP32, periodic along both axes; see steps_per_launch)
+ * the batch kernel advances two steps per launch, else one.  use_graph = 1
+ * (stream must not be NULL) replays a captured graph of sixteen launches
+ * while enough steps remain, then one of two launches, and runs the rest
+ * eagerly (an odd last step with a one-step launch); each graph is captured
+ * on first use and again after the state has moved to the other buffer or
+ * the tile shape changed.  HLBM_EHIP if a capture or launch fails. */
 int hlbm_batch_step(hlbm_batch *b, int32_t nsteps, int32_t use_graph, hlbm_stream_t stream);
 
 /* Concatenated macroscopic fields of all domains (NULL outputs skipped). */
@@ -281,12 +284,14 @@ int hlbm_batch_moments(hlbm_batch *b, void *rho, void *ux, void *uy, void *s, vo
  * diverged domains (>= 0) or an error.  Synchronises `stream`. */
 int hlbm_batch_status(hlbm_batch *b, int32_t *host_flags, hlbm_stream_t stream);
 
-/* Tile shape of the batched kernel: tile_w in {64, 128, 192, 256}, tile_h >= 4.
+/* Tile shape of the batched kernel: tile_w in {64, 128, 192, 256} (64, 128
+ * or 192 for two steps per launch, 64 or 128 in FP64), tile_h >= 4.
  * Synchronises `stream`. */
 int hlbm_batch_set_tile(hlbm_batch *b, int32_t tile_w, int32_t tile_h, hlbm_stream_t stream);
 
-/* Time `steps` steps (after one untimed step) for every tile shape in
- * {64, 128, 192, 256} x {4, 8, 16, 32, 64, 128}, twice each, keep the fastest
+/* Time `steps` steps (after one untimed launch; rounded up to even for two
+ * steps per launch) for every tile shape in {64, 128, 192, 256} x {4, 8,
+ * 16, 32, 64, 128} that the batch kernel has, twice each, keep the fastest
  * and report it.  scratch: a device buffer of hlbm_batch_state_bytes(b) bytes
  * owned by the caller; the state at entry is saved there and loaded again
  * (divergence flags cleared) before every trial, so all shapes time the same
@@ -302,6 +307,11 @@ int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, void *scratch, int32_t *ho
 size_t hlbm_batch_state_bytes(const hlbm_batch *b);
 int hlbm_batch_save_state(hlbm_batch *b, void *dst, hlbm_stream_t stream);
 int hlbm_batch_load_state(hlbm_batch *b, const void *src, hlbm_stream_t stream);
+
+/* Steps per launch of the batch kernel (2 when every domain's own plan is
+ * two steps per launch, else 1) and its current tile shape.  Host-only. */
+int hlbm_batch_plan(const hlbm_batch *b, int32_t *host_steps_per_launch, int32_t *host_tile_w,
+                    int32_t *host_tile_h);
 
 int64_t hlbm_batch_nodes(const hlbm_batch *b);       /* sum of nx ny */
 int64_t hlbm_batch_steps_done(const hlbm_batch *b);

@@ -91,6 +91,8 @@ def lib():
             "hlbm_batch_save_state": (ctypes.c_int, [vp, vp, vp]),
             "hlbm_batch_load_state": (ctypes.c_int, [vp, vp, vp]),
             "hlbm_batch_nodes": (i64, [vp]),
+            "hlbm_batch_plan": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                               ctypes.POINTER(i32)]),
             "hlbm_batch_steps_done": (i64, [vp]),
             "hlbm_batch_destroy": (None, [vp]),
             # learned closure (include/hlbm_nn.h)
@@ -437,6 +439,13 @@ class BatchSolver:
     @property
     def steps(self):
         return int(lib().hlbm_batch_steps_done(self.h))
+
+    def plan(self):
+        """(steps_per_launch, tile_w, tile_h) of the batch kernel."""
+        n, w, h = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().hlbm_batch_plan(self.h, ctypes.byref(n), ctypes.byref(w), ctypes.byref(h)),
+               "hlbm_batch_plan")
+        return int(n.value), int(w.value), int(h.value)
 
     def _enter(self):
         import torch

@@ -493,6 +493,8 @@ struct hlbm_batch {
   size_t total = 0;
   size_t state_bytes = 0;             // one buffer
   int max_items = 0, nitems = 0, tile_w = 128, tile_h = 32, grid = 1, cur = 0, ncu = 1;
+  int spl = 1;    // steps per launch of the batch kernel (2: every domain periodic, FP32)
+  int grid1 = 1;  // persistent grid of the one-step kernel (odd last steps)
   int64_t steps = 0, nodes = 0;
   // captured plain steps: graph[0] one ping-pong pair, graph[1] kLongPairs
   // pairs (fewer replays, so fewer gaps between them, for short steps)
@@ -585,9 +587,15 @@ hipError_t batch_upload_items(hlbm_batch *b, int tw, int th, hipStream_t st) {
   if (e != hipSuccess) return e;
   b->tile_w = tw;
   b->tile_h = th;
-  const int per_cu = b->dtype == HLBM_F64 ? hlbm::f64::batch_blocks_per_cu(tw)
-                                          : hlbm::f32::batch_blocks_per_cu(tw);
-  b->grid = std::max(1, std::min(b->nitems, per_cu * b->ncu));
+  const int per_cu1 = b->dtype == HLBM_F64 ? hlbm::f64::batch_blocks_per_cu(tw)
+                                           : hlbm::f32::batch_blocks_per_cu(tw);
+  b->grid1 = std::max(1, std::min(b->nitems, per_cu1 * b->ncu));
+  b->grid = b->grid1;
+  if (b->spl == 2) {
+    const int per_cu2 = b->dtype == HLBM_F64 ? hlbm::f64::batch2_blocks_per_cu(tw)
+                                             : hlbm::f32::batch2_blocks_per_cu(tw);
+    b->grid = std::max(1, std::min(b->nitems, per_cu2 * b->ncu));
+  }
   for (hipGraphExec_t &g : b->graph) {
     if (g) (void)hipGraphExecDestroy(g);
     g = nullptr;
@@ -639,19 +647,46 @@ hipError_t batch_graph(hlbm_batch *b, int which, int pairs, hipStream_t st) {
   return hipSuccess;
 }
 
-hipError_t batch_launch(hlbm_batch *b, int from, hipStream_t st) {
+hipError_t batch_launch_spl(hlbm_batch *b, int from, int spl, hipStream_t st) {
   const char *src = b->ws + (from ? b->off_buf1 : 0);
   char *dst = b->ws + (from ? 0 : b->off_buf1);
   const long long *offs = (const long long *)(b->ws + b->off_offs);
   unsigned *stat = (unsigned *)(b->ws + b->off_stat);
   const void *items = b->ws + b->off_items;
   const void *doms = b->ws + b->off_doms;
-  // tile_h is carried per item (rows of that domain's strips)
+  if (spl == 2) {
+    if (b->dtype == HLBM_F64)
+      return hlbm::f64::step_batch2(doms, offs, items, b->nitems, src, dst, stat, b->tile_h,
+                                    b->tile_w, b->grid, st);
+    return hlbm::f32::step_batch2(doms, offs, items, b->nitems, src, dst, stat, b->tile_h,
+                                  b->tile_w, b->grid, st);
+  }
   if (b->dtype == HLBM_F64)
     return hlbm::f64::step_batch(doms, offs, items, b->nitems, src, dst, stat, b->tile_h,
-                                 b->tile_w, b->grid, st);
+                                 b->tile_w, b->grid1, st);
   return hlbm::f32::step_batch(doms, offs, items, b->nitems, src, dst, stat, b->tile_h,
-                               b->tile_w, b->grid, st);
+                               b->tile_w, b->grid1, st);
+}
+
+// One launch of the batch's kernel (b->spl steps) from buffer `from`.
+hipError_t batch_launch(hlbm_batch *b, int from, hipStream_t st) {
+  return batch_launch_spl(b, from, b->spl, st);
+}
+
+// `n` steps from buffer b->cur, eagerly: launches of b->spl steps, then a
+// one-step launch for an odd remainder; advances b->cur (not b->steps).
+hipError_t batch_steps_eager(hlbm_batch *b, int n, hipStream_t st) {
+  for (; n >= b->spl; n -= b->spl) {
+    hipError_t e = batch_launch(b, b->cur, st);
+    if (e != hipSuccess) return e;
+    b->cur ^= 1;
+  }
+  for (; n > 0; --n) {
+    hipError_t e = batch_launch_spl(b, b->cur, 1, st);
+    if (e != hipSuccess) return e;
+    b->cur ^= 1;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -685,6 +720,9 @@ int hlbm_batch_init(hlbm_batch **out, const hlbm_params *params, int32_t count, 
     return HLBM_EWORKSPACE;
   }
   b->ws = (char *)workspace;
+  b->spl = 2;  // two steps per launch when every domain would take them alone
+  for (int k = 0; k < count; ++k)
+    if (steps_per_launch(&b->params[k]) != 2) b->spl = 1;
   b->doms.resize(count);
   for (int k = 0; k < count; ++k) {
     fill_domain(&b->params[k], &b->doms[k]);
@@ -739,23 +777,20 @@ int hlbm_batch_step(hlbm_batch *b, int32_t nsteps, int32_t use_graph, hlbm_strea
   if (use_graph && !st) return HLBM_EINVAL;  // the legacy null stream cannot be captured
   int n = nsteps;
   if (use_graph) {
-    // long graphs while at least kLongPairs pairs remain, then single pairs;
-    // an odd last step runs eagerly
+    // long graphs while at least kLongPairs pairs of launches remain, then
+    // single pairs; the rest runs eagerly
     for (int which = 1; which >= 0; --which) {
-      const int len = 2 * (which ? kLongPairs : 1);
+      const int len = 2 * (which ? kLongPairs : 1) * b->spl;
       if (n < len) continue;
-      if (batch_graph(b, which, len / 2, st) != hipSuccess) return HLBM_EHIP;
+      if (batch_graph(b, which, len / (2 * b->spl), st) != hipSuccess) return HLBM_EHIP;
       for (; n >= len; n -= len) {
         if (hipGraphLaunch(b->graph[which], st) != hipSuccess) return HLBM_EHIP;
         b->steps += len;
       }
     }
   }
-  for (; n > 0; --n) {
-    if (batch_launch(b, b->cur, st) != hipSuccess) return HLBM_EHIP;
-    b->cur ^= 1;
-    b->steps++;
-  }
+  if (batch_steps_eager(b, n, st) != hipSuccess) return HLBM_EHIP;
+  b->steps += n;
   return HLBM_OK;
 }
 
@@ -797,6 +832,8 @@ int hlbm_batch_status(hlbm_batch *b, int32_t *host_flags, hlbm_stream_t stream) 
 int hlbm_batch_set_tile(hlbm_batch *b, int32_t tile_w, int32_t tile_h, hlbm_stream_t stream) {
   if (!b) return HLBM_EINVAL;
   if (tile_w != 64 && tile_w != 128 && tile_w != 192 && tile_w != 256) return HLBM_EINVAL;
+  if (b->spl == 2 && (tile_w == 256 || (b->dtype == HLBM_F64 && tile_w == 192)))
+    return HLBM_EINVAL;  // the two-step batch kernel's widths
   if (tile_h < kBatchMinRows) return HLBM_EINVAL;
   return hip_status(batch_upload_items(b, tile_w, tile_h, (hipStream_t)stream));
 }
@@ -806,6 +843,8 @@ int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, void *scratch, int32_t *ho
   if (!b || steps < 1 || !scratch) return HLBM_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const int hs[6] = {4, 8, 16, 32, 64, 128};
+  const int nw = b->spl == 2 ? (b->dtype == HLBM_F64 ? 2 : 3) : 4;  // widths the kernel has
+  if (b->spl == 2 && steps % 2) ++steps;
   constexpr int kRepeats = 2;  // best of two timings per shape
   float best = 1e30f;
   int bw = b->tile_w, bh = b->tile_h;
@@ -819,12 +858,13 @@ int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, void *scratch, int32_t *ho
   // every trial starts from the state at entry, with the divergence flags
   // cleared, so each shape times the same work; the state is restored at the end
   int rc = hlbm_batch_save_state(b, scratch, stream);
-  for (int tw : kBatchTileW) {
+  for (int iw = 0; iw < nw; ++iw) {
+    const int tw = kBatchTileW[iw];
     for (int th : hs) {
       for (int rep = 0; rep < kRepeats && rc == HLBM_OK; ++rep) {
         if (hlbm_batch_load_state(b, scratch, stream) != HLBM_OK) { rc = HLBM_EHIP; break; }
         if (batch_upload_items(b, tw, th, st) != hipSuccess) { rc = HLBM_EHIP; break; }
-        if (hlbm_batch_step(b, 1, 0, st) != HLBM_OK) { rc = HLBM_EHIP; break; }
+        if (hlbm_batch_step(b, b->spl, 0, st) != HLBM_OK) { rc = HLBM_EHIP; break; }
         if (hipEventRecord(e0, st) != hipSuccess) { rc = HLBM_EHIP; break; }
         if (hlbm_batch_step(b, steps, 0, st) != HLBM_OK) { rc = HLBM_EHIP; break; }
         if (hipEventRecord(e1, st) != hipSuccess) { rc = HLBM_EHIP; break; }
@@ -872,6 +912,15 @@ int hlbm_batch_load_state(hlbm_batch *b, const void *src, hlbm_stream_t stream) 
   return hip_status(e);
 }
 
+int hlbm_batch_plan(const hlbm_batch *b, int32_t *host_steps_per_launch, int32_t *host_tile_w,
+                    int32_t *host_tile_h) {
+  if (!b || !host_steps_per_launch || !host_tile_w || !host_tile_h) return HLBM_EINVAL;
+  *host_steps_per_launch = b->spl;
+  *host_tile_w = b->tile_w;
+  *host_tile_h = b->tile_h;
+  return HLBM_OK;
+}
+
 int64_t hlbm_batch_nodes(const hlbm_batch *b) { return b ? b->nodes : -1; }
 
 int64_t hlbm_batch_steps_done(const hlbm_batch *b) { return b ? b->steps : -1; }
@@ -911,10 +960,7 @@ hipError_t correct_launch(hlbm_batch *b, const float *x, const float *delta, int
 // `every` plain steps from buffer b->cur, then the network's correction;
 // advances b->cur
 int closure_once(hlbm_batch *b, hlbm_cnn *c, int every, int conserve, hipStream_t st) {
-  for (int k = 0; k < every; ++k) {
-    if (batch_launch(b, b->cur, st) != hipSuccess) return HLBM_EHIP;
-    b->cur ^= 1;
-  }
+  if (batch_steps_eager(b, every, st) != hipSuccess) return HLBM_EHIP;
   float *x = hlbm_cnn_io(c, 0), *d = hlbm_cnn_io(c, 1);
   const long long n = (long long)b->params[0].nx * b->params[0].ny;
   const long long N = n * b->count;

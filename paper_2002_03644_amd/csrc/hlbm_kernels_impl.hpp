@@ -213,6 +213,45 @@ hipError_t step_batch(const void *doms, const long long *offs, const void *items
   return hipGetLastError();
 }
 
+hipError_t step_batch2(const void *doms, const long long *offs, const void *items, int nitems,
+                       const void *src, void *dst, unsigned *status, int rows, int cw, int grid,
+                       hipStream_t st) {
+  BatchArgs a;
+  a.doms = (const DomainArgs *)doms;
+  a.offs = offs;
+  a.items = (const int4 *)items;
+  a.nitems = nitems;
+  a.src_buf = (const real *)src;
+  a.dst_buf = (real *)dst;
+  a.status = status;
+  a.rows = rows;
+  switch (cw) {
+  case 64:
+    hipLaunchKernelGGL(k_step_batch2<64>, dim3(grid), dim3(64 + 64), 0, st, a);
+    break;
+  case 128:
+    hipLaunchKernelGGL(k_step_batch2<128>, dim3(grid), dim3(128 + 64), 0, st, a);
+    break;
+  case 192:
+    if (sizeof(real) != 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_step_batch2<192>, dim3(grid), dim3(192 + 64), 0, st, a);
+    break;
+  default:
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int batch2_blocks_per_cu(int cw) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (cw == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch2<64>, 128, 0);
+  if (cw == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch2<128>, 192, 0);
+  if (cw == 192 && sizeof(real) == 4)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch2<192>, 256, 0);
+  return e == hipSuccess && n > 0 ? n : 1;
+}
+
 hipError_t correct(const void *doms, const long long *offs, int count, long long n, void *state,
                    const float *x, const float *dl, double *partials, int conserve,
                    hipStream_t st) {

@@ -343,5 +343,24 @@ __global__ __launch_bounds__(CW + 64) void k_step2(StepArgs a) {
   sweep_tile2<CW>(a.d, a.src, a.dst, a.status, a.rows, bid % a.nbx, bid / a.nbx, R);
 }
 
+// Two steps of a batch of periodic domains: the persistent walk over (domain,
+// tile) items of the one-step batch kernel, with the two-step sweep.
+template <int CW>
+__global__ __launch_bounds__(CW + 64) void k_step_batch2(BatchArgs a) {
+  __shared__ TileRings2<CW> R;
+  for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+    const int4 w = a.items[it];
+    const int dm = __builtin_amdgcn_readfirstlane(w.x);
+    // one skip decision per workgroup (see k_step_batch)
+    const int frozen =
+        threadIdx.x == 0 ? (int)(__atomic_load_n(&a.status[dm], __ATOMIC_RELAXED) != 0u) : 0;
+    if (__syncthreads_or(frozen)) continue;
+    const DomainArgs d = a.doms[dm];
+    const long long off = a.offs[dm];
+    sweep_tile2<CW>(d, a.src_buf + off, a.dst_buf + off, a.status + dm, a.rows,
+                    __builtin_amdgcn_readfirstlane(w.y), __builtin_amdgcn_readfirstlane(w.z), R);
+  }
+}
+
 }  // namespace HLBM_NS
 }  // namespace hlbm

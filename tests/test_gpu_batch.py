@@ -1,7 +1,9 @@
-"""Batched engine: one persistent launch per step over many uneven domains.
+"""Batched engine: one persistent launch per step (two steps per launch when
+every domain is periodic and FP32) over many uneven domains.
 
 Per-node arithmetic is the single-domain kernel's, so a batched run must be
-bitwise identical to running each domain alone with the same tile shape."""
+bitwise identical to running each domain alone with the same tile shape and
+the same steps per launch."""
 import dataclasses
 import json
 import os
@@ -19,7 +21,7 @@ from paper_2002_03644_amd import BatchSolver, Params, Solver  # noqa: E402
 SHAPES = [(64, 64), (100, 77), (130, 130), (257, 63), (33, 200), (5, 3), (300, 41)]
 
 
-def domain_set(dtype, poison=None):
+def domain_set(dtype, poison=None, spl=1, periodic=False):
     params, fields = [], []
     for k, (nx, ny) in enumerate(SHAPES):
         mach = 0.2 + 0.15 * k
@@ -31,9 +33,10 @@ def domain_set(dtype, poison=None):
             f = hi.random_smooth(nx, ny, seed=k, amp=0.03, theta0=th, u0=(0.1, -0.05))
         if poison == k:
             f = (f[0], f[1] + 3.0, f[2], f[3])   # CFL far above 1: diverges
-        bc = "extrapolate" if k == 3 else "periodic"
+        bc = "extrapolate" if k == 3 and not periodic else "periodic"
         params.append(Params(nx, ny, dtype=dtype, mu=1e-3 * (1 + k), sigma=0.1 * k,
-                             bc_x=bc, theta_ref=th, tile_w=128, tile_h=32))
+                             bc_x=bc, theta_ref=th, tile_w=128, tile_h=32,
+                             steps_per_launch=spl))
         fields.append(f)
     return params, fields
 
@@ -67,6 +70,26 @@ def test_batch_bitwise_equals_single_domains(dtype, graph, tile):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("graph,tile,steps", [(False, (128, 32), 23), (True, (128, 16), 37),
+                                              (True, (64, 8), 23)])
+def test_two_step_batch_bitwise_equals_single_domains(dtype, graph, tile, steps):
+    """All domains periodic, two steps per launch (an odd count ends with a
+    one-step launch): each domain equals its single run with the same tile
+    and plan, bit for bit."""
+    params, fields = domain_set(dtype, spl=2, periodic=True)
+    B = BatchSolver(params, fields)
+    B.set_tile(*tile)
+    B.step(steps, graph=graph)
+    mb = B.moments()
+    ms = singles([dataclasses.replace(p, tile_w=tile[0], tile_h=tile[1]) for p in params],
+                 fields, steps)
+    for k in range(len(params)):
+        for key in ("rho", "ux", "uy", "s"):
+            assert torch.equal(mb[k][key], ms[k][key]), (k, key)
+    assert B.status()[0] == 0 and B.steps == steps
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_batch_with_mixed_options_equals_single_domains(dtype):
     """Every per-domain option travels in the batch's parameter table: domains
     with precise theta, the original-model ablation (centred E1, no E2),
@@ -82,7 +105,7 @@ def test_batch_with_mixed_options_equals_single_domains(dtype):
         fields.append(hi.vortex(nx, ny, nx / 2, ny / 2, 7, 0.4, 0.04, theta_inf=th,
                                 gamma=o.get("gamma", 1.4), angle=0.4 * k))
         params.append(Params(nx, ny, dtype=dtype, mu=1e-3, sigma=0.25, theta_ref=th,
-                             tile_w=128, tile_h=16, **o))
+                             tile_w=128, tile_h=16, steps_per_launch=1, **o))
     B = BatchSolver(params, fields)
     B.set_tile(128, 16)
     B.step(19, graph=True)

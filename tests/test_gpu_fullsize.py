@@ -1,9 +1,12 @@
 """Parity at full size, in the launch configuration bench.py times.
 
-One step of a node depends only on the state within radius 2, so the oracle
-can check a full-size GPU step on small patches: take the GPU state around a
-sampled node, step the patch once on the CPU, and compare the patch interior
-(nodes at least 2 from the patch edge) with the GPU's next state."""
+One step of a node depends only on the state within radius 2 (two steps:
+radius 4), so the oracle can check a full-size GPU launch on small patches:
+take the GPU state around a sampled node, step the patch once (twice) on the
+CPU, and compare the patch interior (nodes at least 2 (4) from the patch
+edge) with the GPU's state after the launch.  A two-step launch is the
+two-step sweep that bench.py times at 8192^2; a single step after an even
+number of steps is the one-step kernel."""
 import numpy as np
 import pytest
 
@@ -15,11 +18,10 @@ pytestmark = pytest.mark.gpu
 
 from paper_2002_03644_amd import HLBM_OK, Params, Solver  # noqa: E402
 
-P = 12      # patch edge
-INNER = 2   # rim whose nodes see outside the patch
+P1 = 12     # patch edge for one step
 
 
-def take_patch(arr, y0, x0, ny, nx, wrap_y, wrap_x):
+def take_patch(arr, y0, x0, ny, nx, wrap_y, wrap_x, P):
     """arr: torch [..., ny, nx] on the GPU -> numpy FP64 patch [..., P, P]."""
     ys = torch.arange(y0, y0 + P, device=arr.device)
     xs = torch.arange(x0, x0 + P, device=arr.device)
@@ -29,12 +31,16 @@ def take_patch(arr, y0, x0, ny, nx, wrap_y, wrap_x):
     return sub.double().cpu().numpy()
 
 
-def patch_check(S, params, samples, steps_before, tol_F, tol_s, bc_x="periodic"):
+def patch_check(S, params, samples, steps_before, tol_F, tol_s, bc_x="periodic", steps=1):
+    """`steps` (1 or 2) GPU steps in one call after `steps_before`, checked on
+    patches of 12 + 4 (steps - 1) nodes whose rim of 2 steps nodes is left
+    out."""
     nx, ny = params.nx, params.ny
+    P, INNER = P1 + 4 * (steps - 1), 2 * steps
     S.step(steps_before)
     F0 = S.populations()
     s0 = S.moments()["s"]
-    S.step(1)
+    S.step(steps)
     F1 = S.populations()
     s1 = S.moments()["s"]
     assert S.status()[0] == HLBM_OK
@@ -48,17 +54,17 @@ def patch_check(S, params, samples, steps_before, tol_F, tol_s, bc_x="periodic")
             x0 = 0 if x0 < 0 else nx - P
             bx = "extrapolate"
         y0 = y - P // 2
-        pf0 = take_patch(F0, y0, x0, ny, nx, True, bc_x == "periodic")
-        ps0 = take_patch(s0, y0, x0, ny, nx, True, bc_x == "periodic")
-        pf1 = take_patch(F1, y0, x0, ny, nx, True, bc_x == "periodic")
-        ps1 = take_patch(s1, y0, x0, ny, nx, True, bc_x == "periodic")
+        pf0 = take_patch(F0, y0, x0, ny, nx, True, bc_x == "periodic", P)
+        ps0 = take_patch(s0, y0, x0, ny, nx, True, bc_x == "periodic", P)
+        pf1 = take_patch(F1, y0, x0, ny, nx, True, bc_x == "periodic", P)
+        ps1 = take_patch(s1, y0, x0, ny, nx, True, bc_x == "periodic", P)
         op = oracle.OracleParams(P, P, gamma=params.gamma, mu=params.mu, sigma=params.sigma,
                                  prandtl=params.prandtl, phi_mode=params.phi_mode,
                                  bc_x="extrapolate", bc_y="extrapolate", sgn_eps=params.sgn_eps)
         rho = pf0.sum(0)
         O = oracle.OracleSolver(op, rho, np.zeros_like(rho), np.zeros_like(rho), s=ps0)
         O.set_state(pf0, ps0)
-        O.step(1)
+        O.step(steps)
         Fo, so = O.state()
         # interior: at least INNER from every patch edge that is not a true
         # extrapolated boundary of the domain
@@ -73,13 +79,16 @@ def patch_check(S, params, samples, steps_before, tol_F, tol_s, bc_x="periodic")
     print("worst |dF|, |ds|:", worst)
 
 
-def test_f32_turbulence_8192_sampled_one_step():
-    """Decaying turbulence 8192^2, FP32, default tiles (as bench.py: 192 x 16,
-    the last tile column ragged at x = 8064): after 20 steps, one more GPU
-    step matches the oracle's step of the same FP32 state on 88 patches --
-    random nodes plus tile seams (x = 191, 192, 8063, 8064), strip seams
-    (y = 15, 16), the 128 x 32 seams and the periodic corners.  FP32
-    arithmetic: 1e-6 on F (values ~0.01-0.4), 2e-6 on s (|s| ~ 1.3)."""
+@pytest.mark.parametrize("steps", [2, 1])
+def test_f32_turbulence_8192_sampled(steps):
+    """Decaying turbulence 8192^2, FP32, default plan (as bench.py: two steps
+    per launch on 192 x 64 tiles, the last tile column ragged at x = 8064;
+    one step: the one-step kernel on 192 x 16 tiles): after 20 steps, one
+    more launch matches the oracle's steps of the same FP32 state on 96
+    patches -- random nodes plus tile seams (x = 191, 192, 8063, 8064), strip
+    seams (y = 15, 16, 63, 64), the 128 x 32 seams and the periodic corners.
+    FP32 arithmetic: 1e-6 on F (values ~0.01-0.4), 2e-6 on s (|s| ~ 1.3) per
+    step."""
     n = 8192
     r, u, v, t = hi.turbulence(n, 0.5, hi.THETA_PAPER, seed=0)
     params = Params(n, n, dtype="f32", mu=1e-3, sigma=0.0)
@@ -94,8 +103,10 @@ def test_f32_turbulence_8192_sampled_one_step():
                 (31, 128), (32, 127), (4095, 4096), (4096, 4095), (n - 33, 255), (5, 8191),
                 (8191, 3), (100, 128 * 40), (32 * 200, 77), (32 * 255 + 31, 128 * 63 + 127),
                 (15, 191), (16, 192), (15, 192), (16, 191), (16 * 300 + 15, 8063),
-                (16 * 300 + 16, 8064), (8191, 8064), (16 * 511 + 15, 192 * 41 + 191)]
-    patch_check(S, params, samples, 20, tol_F=1e-6, tol_s=2e-6)
+                (16 * 300 + 16, 8064), (8191, 8064), (16 * 511 + 15, 192 * 41 + 191),
+                (63, 191), (64, 192), (63, 192), (64, 191), (64 * 70 + 63, 8063),
+                (64 * 70 + 64, 8064), (64 * 127 + 63, 192 * 41 + 191), (8191, 191)]
+    patch_check(S, params, samples, 20, tol_F=1e-6 * steps, tol_s=2e-6 * steps, steps=steps)
 
 
 def test_f64_mach2_2048x512_sampled_one_step():
@@ -117,8 +128,9 @@ def test_f64_mach2_2048x512_sampled_one_step():
     patch_check(S, params, samples, 50, tol_F=1e-13, tol_s=1e-13, bc_x="extrapolate")
 
 
-@pytest.mark.parametrize("dtype,tol_F,tol_s", [("f64", 1e-13, 1e-13), ("f32", 1e-6, 2e-6)])
-def test_largest_grid_sampled_one_step(dtype, tol_F, tol_s):
+@pytest.mark.parametrize("dtype,tol_F,tol_s,steps", [("f64", 1e-13, 1e-13, 1), ("f32", 1e-6, 2e-6, 1),
+                                                    ("f32", 2e-6, 4e-6, 2)])
+def test_largest_grid_sampled(dtype, tol_F, tol_s, steps):
     """The largest grid the ABI accepts, 15446 x 15446 (9 nx ny just below
     2^31; one FP64 plane is 1.9 GB, so byte offsets reach their limit):
     after 2 steps, one more GPU step matches the oracle on patches at the
@@ -139,6 +151,6 @@ def test_largest_grid_sampled_one_step(dtype, tol_F, tol_s):
     samples = [(int(a), int(b)) for a, b in rng.integers(0, n, size=(8, 2))]
     samples += [(n - 1, n - 1), (n - 2, n - 3), (n - 1, 0), (0, n - 1), (n // 2, n // 2),
                 (n - 7, 15000), (15000, n - 7), (0, 0)]
-    patch_check(S, params, samples, 2, tol_F=tol_F, tol_s=tol_s)
+    patch_check(S, params, samples, 2, tol_F=tol_F, tol_s=tol_s, steps=steps)
     del S
     torch.cuda.empty_cache()
