@@ -83,25 +83,31 @@ hipError_t step2(const HostDomain &h, const void *src, void *dst, unsigned *stat
   a.nbx = (h.nx + tile.bw - 1) / tile.bw;
   a.nby = (h.ny + tile.rows - 1) / tile.rows;
   a.xcd_remap = tile.xcd_remap;
-  const int nblk = a.nbx * a.nby;
-  switch (tile.bw) {
-  case 64:
-    hipLaunchKernelGGL(k_step2<64>, dim3(nblk), dim3(64 + 64), 0, st, a);
+  const dim3 grid(a.nbx * a.nby);
+#define HLBM_STEP2_CASE(CW)                                                                  \
+  case CW:                                                                                   \
+    hipLaunchKernelGGL(k_step2<CW>, grid, dim3(step2_threads(CW)), 0, st, a);                \
     break;
-  case 128:
-    hipLaunchKernelGGL(k_step2<128>, dim3(nblk), dim3(128 + 64), 0, st, a);
-    break;
-  case 192:
-    if (sizeof(real) != 4) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_step2<192>, dim3(nblk), dim3(192 + 64), 0, st, a);
-    break;
-  case 256:
-    if (sizeof(real) != 4) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_step2<256>, dim3(nblk), dim3(256 + 64), 0, st, a);
-    break;
-  default:
-    return hipErrorInvalidValue;
+  if (sizeof(real) == 4) {
+    switch (tile.bw) {
+      HLBM_STEP2_CASE(64)
+      HLBM_STEP2_CASE(128)
+      HLBM_STEP2_CASE(184)
+      HLBM_STEP2_CASE(192)
+      HLBM_STEP2_CASE(248)
+      HLBM_STEP2_CASE(256)
+    default:
+      return hipErrorInvalidValue;
+    }
+  } else {
+    switch (tile.bw) {
+      HLBM_STEP2_CASE(64)
+      HLBM_STEP2_CASE(128)
+    default:
+      return hipErrorInvalidValue;
+    }
   }
+#undef HLBM_STEP2_CASE
   return hipGetLastError();
 }
 
@@ -225,30 +231,41 @@ hipError_t step_batch2(const void *doms, const long long *offs, const void *item
   a.dst_buf = (real *)dst;
   a.status = status;
   a.rows = rows;
-  switch (cw) {
-  case 64:
-    hipLaunchKernelGGL(k_step_batch2<64>, dim3(grid), dim3(64 + 64), 0, st, a);
+#define HLBM_BATCH2_CASE(CW)                                                                 \
+  case CW:                                                                                   \
+    hipLaunchKernelGGL(k_step_batch2<CW>, dim3(grid), dim3(step2_threads(CW)), 0, st, a);    \
     break;
-  case 128:
-    hipLaunchKernelGGL(k_step_batch2<128>, dim3(grid), dim3(128 + 64), 0, st, a);
-    break;
-  case 192:
-    if (sizeof(real) != 4) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_step_batch2<192>, dim3(grid), dim3(192 + 64), 0, st, a);
-    break;
-  default:
-    return hipErrorInvalidValue;
+  if (sizeof(real) == 4) {
+    switch (cw) {
+      HLBM_BATCH2_CASE(64)
+      HLBM_BATCH2_CASE(128)
+      HLBM_BATCH2_CASE(192)
+    default:
+      return hipErrorInvalidValue;
+    }
+  } else {
+    switch (cw) {
+      HLBM_BATCH2_CASE(64)
+      HLBM_BATCH2_CASE(128)
+    default:
+      return hipErrorInvalidValue;
+    }
   }
+#undef HLBM_BATCH2_CASE
   return hipGetLastError();
 }
 
 int batch2_blocks_per_cu(int cw) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
-  if (cw == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch2<64>, 128, 0);
-  if (cw == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch2<128>, 192, 0);
+  if (cw == 64)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch2<64>, step2_threads(64), 0);
+  if (cw == 128)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch2<128>, step2_threads(128),
+                                                     0);
   if (cw == 192 && sizeof(real) == 4)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch2<192>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch2<192>, step2_threads(192),
+                                                     0);
   return e == hipSuccess && n > 0 ? n : 1;
 }
 

@@ -55,6 +55,10 @@ struct TileRings2 {
   LevelRings<W> L1, L2;
 };
 
+// Threads of a two-step workgroup: the tile's CW columns and the 8 halo
+// columns, rounded up to whole waves.
+constexpr int step2_threads(int cw) { return (cw + 8 + 63) / 64 * 64; }
+
 // Per-lane registers of one time level: the node state of rows k and k + 1
 // carried from A to B, B's y-stencil along the lane's column, and the B -> C
 // carries with populations 0, 2 and 4 (see the one-step sweep).
@@ -330,7 +334,7 @@ __device__ __forceinline__ void sweep_tile2(const DomainArgs &d, const real *src
 
 // Two steps of a whole periodic domain: one workgroup per tile.
 template <int CW>
-__global__ __launch_bounds__(CW + 64) void k_step2(StepArgs a) {
+__global__ __launch_bounds__(step2_threads(CW)) void k_step2(StepArgs a) {
   __shared__ TileRings2<CW> R;
   int bid = blockIdx.x;
   const int nblk = a.nbx * a.nby;
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(CW + 64) void k_step2(StepArgs a) {
 // Two steps of a batch of periodic domains: the persistent walk over (domain,
 // tile) items of the one-step batch kernel, with the two-step sweep.
 template <int CW>
-__global__ __launch_bounds__(CW + 64) void k_step_batch2(BatchArgs a) {
+__global__ __launch_bounds__(step2_threads(CW)) void k_step_batch2(BatchArgs a) {
   __shared__ TileRings2<CW> R;
   for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
     const int4 w = a.items[it];
