@@ -178,6 +178,8 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--tile-w", type=int, default=0)
     ap.add_argument("--tile-h", type=int, default=0)
+    ap.add_argument("--batch-kernel", default="strips", choices=["strips", "tiles"],
+                    help="batch workload with --tile-w/--tile-h: the kernel those name")
     ap.add_argument("--steps-per-launch", type=int, default=0, choices=[0, 1, 2],
                     help="0: the library's plan (two steps per launch here), 1 or 2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -400,7 +402,7 @@ def bench_closure(args):
         fields.append(tuple(np.ascontiguousarray(a[::f, ::f]) for a in (r, u, v, t)))
         params.append(L._params(nc, setup.mu_coarse, float(t[0, 0]), setup))
     B = BatchSolver(params, fields)
-    tw, th = B.autotune(steps=10)
+    bk, tw, th = B.autotune(steps=10)
     net = CNN(len(seeds), nc, nc, L.initial_params(0))
     net.set_norm(np.array([1, 0, 0, 0.2], np.float32), np.array([0.1, 0.1, 0.1, 0.01], np.float32),
                  np.zeros(4, np.float32), np.array([1e-3, 1e-3, 1e-3, 1e-4], np.float32))
@@ -441,7 +443,7 @@ def bench_closure(args):
            "ms_per_step": round(ms_c / args.steps, 5), "higher_is_better": False,
            "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
            "config": {"workload": "8 periodic 256^2 turbulence domains, learned closure",
-                      "tile_w": tw, "tile_h": th},
+                      "batch_kernel": bk, "tile_w": tw, "tile_h": th},
            "plain_step_us": round(ms_p / args.steps * 1e3, 2),
            "train_step_us_batch16": round(ms_t / nt * 1e3, 1),
            "network_flop_per_field": fwd_flop,
@@ -569,13 +571,12 @@ def bench_batch(args):
     fields = [hi.batch_domain_fields(sp) for sp in specs]
     B = BatchSolver(params, fields)
     if args.tile_w and args.tile_h:
-        B.set_tile(args.tile_w, args.tile_h)
-        tw, th = args.tile_w, args.tile_h
+        B.set_tile(args.tile_w, args.tile_h, args.batch_kernel)
     else:
-        tw, th = B.autotune(steps=10)
+        B.autotune(steps=10)
+    spl, bk, tw, th = B.plan()
     sizes = np.array([p.nx * p.ny for p in params], dtype=np.int64)
     W, K = args.warmup, args.steps
-    spl = B.plan()[0]
     # untimed pass over the same sequence of launches as the timed run (the
     # graphs replay the same kernels): spl-step launches, then one-step
     # launches for a remainder, for the warm-up and then the timed steps.
@@ -631,7 +632,7 @@ def bench_batch(args):
                       "domains_diverged_by_end": int(bad),
                       "domains_active_whole_window": int((div == never).sum()),
                       "divergence_steps_reproduced": deterministic,
-                      "steps_per_launch": spl, "tile_w": tw, "tile_h": th},
+                      "steps_per_launch": spl, "batch_kernel": bk, "tile_w": tw, "tile_h": th},
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                         "traffic": None,

@@ -255,6 +255,17 @@ int hlbm_entropy_from_theta(int32_t dtype, double gamma, const void *rho, const 
  * ------------------------------------------------------------------------ */
 typedef struct hlbm_batch hlbm_batch;
 
+/* Kernels of the batched step.  Both compute the step of Sec. 3 node by node
+ * exactly as hlbm_step's one-step kernel does (FP64 results are bitwise
+ * equal); they differ in how the work is cut:
+ *   HLBM_BATCH_STRIPS  row strips of tile_w columns and tile_h rows swept
+ *                      through the stages (two steps per launch when every
+ *                      domain's own plan has two);
+ *   HLBM_BATCH_TILES   tile_w x tile_h tiles whose halo is loaded at once,
+ *                      one step per launch: less recomputed halo, for
+ *                      domains too small to give long strips. */
+typedef enum { HLBM_BATCH_STRIPS = 0, HLBM_BATCH_TILES = 1 } hlbm_batch_kernel;
+
 /* Workspace bytes for `count` domains, or 0 if any parameter set is invalid,
  * has walls (bc_y = HLBM_BC_WALL is not available in batches) or the dtypes
  * differ.  Host-only. */
@@ -284,23 +295,31 @@ int hlbm_batch_moments(hlbm_batch *b, void *rho, void *ux, void *uy, void *s, vo
  * diverged domains (>= 0) or an error.  Synchronises `stream`. */
 int hlbm_batch_status(hlbm_batch *b, int32_t *host_flags, hlbm_stream_t stream);
 
-/* Tile shape of the batched kernel: tile_w in {64, 128, 192, 256} (64, 128
- * or 192 for two steps per launch, 64 or 128 in FP64), tile_h >= 4.
- * Synchronises `stream`. */
+/* Kernel and tile shape of the batched step.  HLBM_BATCH_STRIPS: tile_w in
+ * {64, 128, 192, 256} (64, 128 or 192 for two steps per launch, 64 or 128
+ * then in FP64), tile_h >= 4.  HLBM_BATCH_TILES: (tile_w, tile_h) in
+ * {(32, 8), (32, 16), (64, 8), (32, 32), (64, 16)}, the first three in FP64.
+ * HLBM_EINVAL for any other shape.  Drops the captured graphs.  Synchronises
+ * `stream`. */
+int hlbm_batch_set_shape(hlbm_batch *b, int32_t kernel, int32_t tile_w, int32_t tile_h,
+                         hlbm_stream_t stream);
+
+/* hlbm_batch_set_shape(b, HLBM_BATCH_STRIPS, tile_w, tile_h, stream). */
 int hlbm_batch_set_tile(hlbm_batch *b, int32_t tile_w, int32_t tile_h, hlbm_stream_t stream);
 
-/* Time `steps` steps (after one untimed launch; rounded up to even for two
- * steps per launch) for every tile shape in {64, 128, 192, 256} x {4, 8,
- * 16, 32, 64, 128} that the batch kernel has, twice each, keep the fastest
- * and report it.  scratch: a device buffer of hlbm_batch_state_bytes(b) bytes
+/* Time `steps` steps (after one untimed launch; rounded up to even when the
+ * strip kernel takes two steps per launch) for every shape that
+ * hlbm_batch_set_shape accepts among strips {64, 128, 192, 256} x {4, 8, 16,
+ * 32, 64, 128} and all tile shapes, twice each, keep the fastest and report
+ * its kernel and shape (outputs may be NULL).  scratch: a device buffer of hlbm_batch_state_bytes(b) bytes
  * owned by the caller; the state at entry is saved there and loaded again
  * (divergence flags cleared) before every trial, so all shapes time the same
  * work, and once more at the end: the domains, their flags and the step
  * count are left as they were (the graphs are dropped and re-captured on the
  * next hlbm_batch_step).  HLBM_EINVAL if scratch is NULL.  Synchronises
  * `stream`. */
-int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, void *scratch, int32_t *host_best_w,
-                        int32_t *host_best_h, hlbm_stream_t stream);
+int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, void *scratch, int32_t *host_best_kernel,
+                        int32_t *host_best_w, int32_t *host_best_h, hlbm_stream_t stream);
 
 /* Raw state of all domains (for checkpoint, or around hlbm_batch_autotune);
  * load also clears the divergence flags. */
@@ -308,10 +327,11 @@ size_t hlbm_batch_state_bytes(const hlbm_batch *b);
 int hlbm_batch_save_state(hlbm_batch *b, void *dst, hlbm_stream_t stream);
 int hlbm_batch_load_state(hlbm_batch *b, const void *src, hlbm_stream_t stream);
 
-/* Steps per launch of the batch kernel (2 when every domain's own plan is
- * two steps per launch, else 1) and its current tile shape.  Host-only. */
-int hlbm_batch_plan(const hlbm_batch *b, int32_t *host_steps_per_launch, int32_t *host_tile_w,
-                    int32_t *host_tile_h);
+/* Steps per launch of the current batch kernel (2 for strips when every
+ * domain's own plan is two steps per launch, else 1), the kernel
+ * (hlbm_batch_kernel) and its tile shape.  Host-only. */
+int hlbm_batch_plan(const hlbm_batch *b, int32_t *host_steps_per_launch, int32_t *host_kernel,
+                    int32_t *host_tile_w, int32_t *host_tile_h);
 
 int64_t hlbm_batch_nodes(const hlbm_batch *b);       /* sum of nx ny */
 int64_t hlbm_batch_steps_done(const hlbm_batch *b);

@@ -20,6 +20,8 @@ HLBM_EINVAL, HLBM_EWORKSPACE, HLBM_EHIP, HLBM_EDIVERGED, HLBM_ENOMEM = -1, -2, -
 F64, F32 = 0, 1
 BC = {"periodic": 0, "extrapolate": 1, "wall": 2}
 PHI = {"lbm": 0, "fd": 1}
+BATCH_KERNELS = {"strips": 0, "tiles": 1}   # hlbm_batch_kernel
+BATCH_KERNEL_NAMES = {v: k for k, v in BATCH_KERNELS.items()}
 
 
 class HlbmError(RuntimeError):
@@ -85,14 +87,15 @@ def lib():
             "hlbm_batch_moments": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
             "hlbm_batch_status": (ctypes.c_int, [vp, ctypes.POINTER(i32), vp]),
             "hlbm_batch_set_tile": (ctypes.c_int, [vp, i32, i32, vp]),
+            "hlbm_batch_set_shape": (ctypes.c_int, [vp, i32, i32, i32, vp]),
             "hlbm_batch_autotune": (ctypes.c_int, [vp, i32, vp, ctypes.POINTER(i32),
-                                                   ctypes.POINTER(i32), vp]),
+                                                   ctypes.POINTER(i32), ctypes.POINTER(i32), vp]),
             "hlbm_batch_state_bytes": (sz, [vp]),
             "hlbm_batch_save_state": (ctypes.c_int, [vp, vp, vp]),
             "hlbm_batch_load_state": (ctypes.c_int, [vp, vp, vp]),
             "hlbm_batch_nodes": (i64, [vp]),
             "hlbm_batch_plan": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                               ctypes.POINTER(i32)]),
+                                               ctypes.POINTER(i32), ctypes.POINTER(i32)]),
             "hlbm_batch_steps_done": (i64, [vp]),
             "hlbm_batch_destroy": (None, [vp]),
             # learned closure (include/hlbm_nn.h)
@@ -441,11 +444,12 @@ class BatchSolver:
         return int(lib().hlbm_batch_steps_done(self.h))
 
     def plan(self):
-        """(steps_per_launch, tile_w, tile_h) of the batch kernel."""
-        n, w, h = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().hlbm_batch_plan(self.h, ctypes.byref(n), ctypes.byref(w), ctypes.byref(h)),
-               "hlbm_batch_plan")
-        return int(n.value), int(w.value), int(h.value)
+        """(steps_per_launch, kernel, tile_w, tile_h) of the batch kernel;
+        kernel is "strips" or "tiles" (see set_tile)."""
+        n, k, w, h = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().hlbm_batch_plan(self.h, ctypes.byref(n), ctypes.byref(k), ctypes.byref(w),
+                                     ctypes.byref(h)), "hlbm_batch_plan")
+        return int(n.value), BATCH_KERNEL_NAMES[k.value], int(w.value), int(h.value)
 
     def _enter(self):
         import torch
@@ -498,10 +502,15 @@ class BatchSolver:
                      "hlbm_batch_status")
         return bad, np.array(flags[:], dtype=np.int32)
 
-    def set_tile(self, tile_w, tile_h):
+    def set_tile(self, tile_w, tile_h, kernel="strips"):
+        """Kernel of the batched step and its tile shape: "strips" (row
+        strips of tile_w columns, tile_h rows) or "tiles" (tile_w x tile_h
+        tiles, one step per launch)."""
+        if kernel not in BATCH_KERNELS:
+            raise ValueError(f"batch kernel {kernel!r}: expected one of {sorted(BATCH_KERNELS)}")
         self._enter()
-        _check(lib().hlbm_batch_set_tile(self.h, int(tile_w), int(tile_h), _stream(self.stream)),
-               "hlbm_batch_set_tile")
+        _check(lib().hlbm_batch_set_shape(self.h, BATCH_KERNELS[kernel], int(tile_w), int(tile_h),
+                                          _stream(self.stream)), "hlbm_batch_set_shape")
 
     def save_state(self):
         import torch
@@ -547,33 +556,36 @@ class BatchSolver:
         return hashlib.sha256(key.encode()).hexdigest()[:20]
 
     def autotune(self, steps=10, cache_path=None):
-        """Pick the fastest tile shape by timing; every shape is timed from the
-        same state, which is restored afterwards (flags and step count too).
-        With ``cache_path`` the choice is read from / written to a JSON file
-        keyed by the batch's domain sizes and dtype."""
+        """Pick the fastest kernel and tile shape by timing and return
+        (kernel, tile_w, tile_h); every shape is timed from the same state,
+        which is restored afterwards (flags and step count too).  With
+        ``cache_path`` the choice is read from / written to a JSON file keyed
+        by the batch's domain sizes and dtype."""
         import json
         sig = self.signature()
         cache = {}
         if cache_path and os.path.exists(cache_path):
             with open(cache_path) as fh:
                 cache = json.load(fh)
-            if sig in cache:
-                w, h = cache[sig]
-                self.set_tile(w, h)
-                return int(w), int(h)
+            if sig in cache and len(cache[sig]) == 3:
+                k, w, h = cache[sig]
+                self.set_tile(w, h, k)
+                return k, int(w), int(h)
         import torch
         scratch = torch.empty(lib().hlbm_batch_state_bytes(self.h), dtype=torch.uint8,
                               device=self.device)
-        bw, bh = ctypes.c_int32(0), ctypes.c_int32(0)
+        bk, bw, bh = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
         self._enter()
-        _check(lib().hlbm_batch_autotune(self.h, int(steps), _ptr(scratch), ctypes.byref(bw),
+        _check(lib().hlbm_batch_autotune(self.h, int(steps), _ptr(scratch), ctypes.byref(bk),
+                                         ctypes.byref(bw),
                                          ctypes.byref(bh), _stream(self.stream)),
                "hlbm_batch_autotune")
         self._leave()
         del scratch
+        kernel = BATCH_KERNEL_NAMES[bk.value]
         if cache_path:
-            cache[sig] = [bw.value, bh.value]
+            cache[sig] = [kernel, bw.value, bh.value]
             os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
             with open(cache_path, "w") as fh:
                 json.dump(cache, fh, indent=1)
-        return bw.value, bh.value
+        return kernel, bw.value, bh.value

@@ -495,7 +495,9 @@ struct hlbm_batch {
   size_t total = 0;
   size_t state_bytes = 0;             // one buffer
   int max_items = 0, nitems = 0, tile_w = 128, tile_h = 32, grid = 1, cur = 0, ncu = 1;
-  int spl = 1;    // steps per launch of the batch kernel (2: every domain periodic, FP32)
+  int kind = HLBM_BATCH_STRIPS;  // kernel: row strips or two-dimensional tiles
+  int spl = 1;         // steps per launch of the current kernel
+  int spl_strips = 1;  // steps per launch of the strip kernel (2: every domain periodic, FP32)
   int grid1 = 1;  // persistent grid of the one-step kernel (odd last steps)
   int64_t steps = 0, nodes = 0;
   // captured plain steps: graph[0] one ping-pong pair, graph[1] kLongPairs
@@ -511,6 +513,8 @@ namespace {
 
 constexpr int kBatchTileW[4] = {64, 128, 192, 256};
 constexpr int kBatchMinRows = 4;  // short strips: small domains are bound by the serial sweep
+// shapes of the two-dimensional tile kernel, tried in this order by the autotuner
+constexpr int kTileShapes[5][2] = {{32, 8}, {32, 16}, {64, 8}, {32, 32}, {64, 16}};
 
 int batch_items_for(const hlbm_batch *b, int tw, int th, std::vector<int> *out) {
   // largest domains first: the round-robin walk then ends on small items
@@ -554,7 +558,9 @@ void batch_layout(hlbm_batch *b) {
   }
   b->nodes = facc;
   b->state_bytes = round_up((size_t)acc * el, kAlign);
-  b->max_items = batch_items_for(b, 64, kBatchMinRows, nullptr);
+  // the most items any shape gives: the narrowest strips or the smallest tiles
+  b->max_items = std::max(batch_items_for(b, 64, kBatchMinRows, nullptr),
+                          batch_items_for(b, 32, 8, nullptr));
   b->off_buf1 = b->state_bytes;
   b->off_doms = 2 * b->state_bytes;
   const size_t dbytes = std::max(hlbm::f32::domain_args_bytes(), hlbm::f64::domain_args_bytes());
@@ -578,7 +584,20 @@ int batch_validate(const hlbm_params *p, int32_t count) {
   return HLBM_OK;
 }
 
-hipError_t batch_upload_items(hlbm_batch *b, int tw, int th, hipStream_t st) {
+bool batch_shape_ok(const hlbm_batch *b, int kind, int tw, int th) {
+  if (kind == HLBM_BATCH_TILES)
+    return b->dtype == HLBM_F64 ? hlbm::f64::tile_shape_supported(tw, th)
+                                : hlbm::f32::tile_shape_supported(tw, th);
+  if (kind != HLBM_BATCH_STRIPS) return false;
+  if (tw != 64 && tw != 128 && tw != 192 && tw != 256) return false;
+  if (b->spl_strips == 2 && (tw == 256 || (b->dtype == HLBM_F64 && tw == 192)))
+    return false;  // the two-step strip kernel's widths
+  return th >= kBatchMinRows;
+}
+
+// Item list and grids of shape (kind, tw, th); the shape must be one
+// batch_shape_ok accepts.
+hipError_t batch_upload_items(hlbm_batch *b, int kind, int tw, int th, hipStream_t st) {
   std::vector<int> items;
   items.reserve(4 * (size_t)b->max_items);
   b->nitems = batch_items_for(b, tw, th, &items);
@@ -587,10 +606,17 @@ hipError_t batch_upload_items(hlbm_batch *b, int tw, int th, hipStream_t st) {
                                 hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);  // host vector must outlive the copy
   if (e != hipSuccess) return e;
+  b->kind = kind;
   b->tile_w = tw;
   b->tile_h = th;
-  const int per_cu1 = b->dtype == HLBM_F64 ? hlbm::f64::batch_blocks_per_cu(tw)
-                                           : hlbm::f32::batch_blocks_per_cu(tw);
+  b->spl = kind == HLBM_BATCH_TILES ? 1 : b->spl_strips;
+  int per_cu1;
+  if (kind == HLBM_BATCH_TILES)
+    per_cu1 = b->dtype == HLBM_F64 ? hlbm::f64::tile_blocks_per_cu(tw, th)
+                                   : hlbm::f32::tile_blocks_per_cu(tw, th);
+  else
+    per_cu1 = b->dtype == HLBM_F64 ? hlbm::f64::batch_blocks_per_cu(tw)
+                                   : hlbm::f32::batch_blocks_per_cu(tw);
   b->grid1 = std::max(1, std::min(b->nitems, per_cu1 * b->ncu));
   b->grid = b->grid1;
   if (b->spl == 2) {
@@ -656,6 +682,13 @@ hipError_t batch_launch_spl(hlbm_batch *b, int from, int spl, hipStream_t st) {
   unsigned *stat = (unsigned *)(b->ws + b->off_stat);
   const void *items = b->ws + b->off_items;
   const void *doms = b->ws + b->off_doms;
+  if (b->kind == HLBM_BATCH_TILES) {  // one step per launch
+    if (b->dtype == HLBM_F64)
+      return hlbm::f64::step_tile_batch(doms, offs, items, b->nitems, src, dst, stat, b->tile_w,
+                                        b->tile_h, b->grid1, st);
+    return hlbm::f32::step_tile_batch(doms, offs, items, b->nitems, src, dst, stat, b->tile_w,
+                                      b->tile_h, b->grid1, st);
+  }
   if (spl == 2) {
     if (b->dtype == HLBM_F64)
       return hlbm::f64::step_batch2(doms, offs, items, b->nitems, src, dst, stat, b->tile_h,
@@ -722,9 +755,10 @@ int hlbm_batch_init(hlbm_batch **out, const hlbm_params *params, int32_t count, 
     return HLBM_EWORKSPACE;
   }
   b->ws = (char *)workspace;
-  b->spl = 2;  // two steps per launch when every domain would take them alone
+  b->spl_strips = 2;  // two steps per launch when every domain would take them alone
   for (int k = 0; k < count; ++k)
-    if (steps_per_launch(&b->params[k]) != 2) b->spl = 1;
+    if (steps_per_launch(&b->params[k]) != 2) b->spl_strips = 1;
+  b->spl = b->spl_strips;
   b->doms.resize(count);
   for (int k = 0; k < count; ++k) {
     fill_domain(&b->params[k], &b->doms[k]);
@@ -764,7 +798,7 @@ int hlbm_batch_init(hlbm_batch **out, const hlbm_params *params, int32_t count, 
     e = b->dtype == HLBM_F64 ? hlbm::f64::init(b->doms[k], r, u, v, sv, dst, st)
                              : hlbm::f32::init(b->doms[k], r, u, v, sv, dst, st);
   }
-  if (e == hipSuccess) e = batch_upload_items(b, 128, 32, st);  // synchronises
+  if (e == hipSuccess) e = batch_upload_items(b, HLBM_BATCH_STRIPS, 128, 32, st);  // synchronises
   if (e != hipSuccess) {
     delete b;
     return HLBM_EHIP;
@@ -831,25 +865,35 @@ int hlbm_batch_status(hlbm_batch *b, int32_t *host_flags, hlbm_stream_t stream) 
   return bad;
 }
 
-int hlbm_batch_set_tile(hlbm_batch *b, int32_t tile_w, int32_t tile_h, hlbm_stream_t stream) {
-  if (!b) return HLBM_EINVAL;
-  if (tile_w != 64 && tile_w != 128 && tile_w != 192 && tile_w != 256) return HLBM_EINVAL;
-  if (b->spl == 2 && (tile_w == 256 || (b->dtype == HLBM_F64 && tile_w == 192)))
-    return HLBM_EINVAL;  // the two-step batch kernel's widths
-  if (tile_h < kBatchMinRows) return HLBM_EINVAL;
-  return hip_status(batch_upload_items(b, tile_w, tile_h, (hipStream_t)stream));
+int hlbm_batch_set_shape(hlbm_batch *b, int32_t kernel, int32_t tile_w, int32_t tile_h,
+                         hlbm_stream_t stream) {
+  if (!b || !batch_shape_ok(b, kernel, tile_w, tile_h)) return HLBM_EINVAL;
+  return hip_status(batch_upload_items(b, kernel, tile_w, tile_h, (hipStream_t)stream));
 }
 
-int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, void *scratch, int32_t *host_best_w,
-                        int32_t *host_best_h, hlbm_stream_t stream) {
+int hlbm_batch_set_tile(hlbm_batch *b, int32_t tile_w, int32_t tile_h, hlbm_stream_t stream) {
+  return hlbm_batch_set_shape(b, HLBM_BATCH_STRIPS, tile_w, tile_h, stream);
+}
+
+int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, void *scratch, int32_t *host_best_kernel,
+                        int32_t *host_best_w, int32_t *host_best_h, hlbm_stream_t stream) {
   if (!b || steps < 1 || !scratch) return HLBM_EINVAL;
   hipStream_t st = (hipStream_t)stream;
-  const int hs[6] = {4, 8, 16, 32, 64, 128};
-  const int nw = b->spl == 2 ? (b->dtype == HLBM_F64 ? 2 : 3) : 4;  // widths the kernel has
-  if (b->spl == 2 && steps % 2) ++steps;
+  // candidate shapes: strips {64, 128, 192, 256} x {4, ..., 128}, then tiles
+  struct Shape {
+    int kind, w, h;
+  };
+  std::vector<Shape> cand;
+  for (int tw : kBatchTileW)
+    for (int th : {4, 8, 16, 32, 64, 128})
+      if (batch_shape_ok(b, HLBM_BATCH_STRIPS, tw, th)) cand.push_back({HLBM_BATCH_STRIPS, tw, th});
+  for (const auto &t : kTileShapes)
+    if (batch_shape_ok(b, HLBM_BATCH_TILES, t[0], t[1]))
+      cand.push_back({HLBM_BATCH_TILES, t[0], t[1]});
+  if (b->spl_strips == 2 && steps % 2) ++steps;  // whole launches of either kernel
   constexpr int kRepeats = 2;  // best of two timings per shape
   float best = 1e30f;
-  int bw = b->tile_w, bh = b->tile_h;
+  Shape bs{b->kind, b->tile_w, b->tile_h};
   const int64_t steps0 = b->steps;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return HLBM_EHIP;
@@ -860,24 +904,20 @@ int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, void *scratch, int32_t *ho
   // every trial starts from the state at entry, with the divergence flags
   // cleared, so each shape times the same work; the state is restored at the end
   int rc = hlbm_batch_save_state(b, scratch, stream);
-  for (int iw = 0; iw < nw; ++iw) {
-    const int tw = kBatchTileW[iw];
-    for (int th : hs) {
-      for (int rep = 0; rep < kRepeats && rc == HLBM_OK; ++rep) {
-        if (hlbm_batch_load_state(b, scratch, stream) != HLBM_OK) { rc = HLBM_EHIP; break; }
-        if (batch_upload_items(b, tw, th, st) != hipSuccess) { rc = HLBM_EHIP; break; }
-        if (hlbm_batch_step(b, b->spl, 0, st) != HLBM_OK) { rc = HLBM_EHIP; break; }
-        if (hipEventRecord(e0, st) != hipSuccess) { rc = HLBM_EHIP; break; }
-        if (hlbm_batch_step(b, steps, 0, st) != HLBM_OK) { rc = HLBM_EHIP; break; }
-        if (hipEventRecord(e1, st) != hipSuccess) { rc = HLBM_EHIP; break; }
-        if (hipEventSynchronize(e1) != hipSuccess) { rc = HLBM_EHIP; break; }
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = HLBM_EHIP; break; }
-        if (ms < best) {
-          best = ms;
-          bw = tw;
-          bh = th;
-        }
+  for (const Shape &c : cand) {
+    for (int rep = 0; rep < kRepeats && rc == HLBM_OK; ++rep) {
+      if (hlbm_batch_load_state(b, scratch, stream) != HLBM_OK) { rc = HLBM_EHIP; break; }
+      if (batch_upload_items(b, c.kind, c.w, c.h, st) != hipSuccess) { rc = HLBM_EHIP; break; }
+      if (hlbm_batch_step(b, b->spl, 0, st) != HLBM_OK) { rc = HLBM_EHIP; break; }
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = HLBM_EHIP; break; }
+      if (hlbm_batch_step(b, steps, 0, st) != HLBM_OK) { rc = HLBM_EHIP; break; }
+      if (hipEventRecord(e1, st) != hipSuccess) { rc = HLBM_EHIP; break; }
+      if (hipEventSynchronize(e1) != hipSuccess) { rc = HLBM_EHIP; break; }
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = HLBM_EHIP; break; }
+      if (ms < best) {
+        best = ms;
+        bs = c;
       }
     }
     if (rc != HLBM_OK) break;
@@ -887,9 +927,10 @@ int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, void *scratch, int32_t *ho
   if (rc != HLBM_OK) return rc;
   if (hlbm_batch_load_state(b, scratch, stream) != HLBM_OK) return HLBM_EHIP;
   b->steps = steps0;
-  if (batch_upload_items(b, bw, bh, st) != hipSuccess) return HLBM_EHIP;
-  if (host_best_w) *host_best_w = bw;
-  if (host_best_h) *host_best_h = bh;
+  if (batch_upload_items(b, bs.kind, bs.w, bs.h, st) != hipSuccess) return HLBM_EHIP;
+  if (host_best_kernel) *host_best_kernel = bs.kind;
+  if (host_best_w) *host_best_w = bs.w;
+  if (host_best_h) *host_best_h = bs.h;
   return HLBM_OK;
 }
 
@@ -914,10 +955,12 @@ int hlbm_batch_load_state(hlbm_batch *b, const void *src, hlbm_stream_t stream) 
   return hip_status(e);
 }
 
-int hlbm_batch_plan(const hlbm_batch *b, int32_t *host_steps_per_launch, int32_t *host_tile_w,
-                    int32_t *host_tile_h) {
-  if (!b || !host_steps_per_launch || !host_tile_w || !host_tile_h) return HLBM_EINVAL;
+int hlbm_batch_plan(const hlbm_batch *b, int32_t *host_steps_per_launch, int32_t *host_kernel,
+                    int32_t *host_tile_w, int32_t *host_tile_h) {
+  if (!b || !host_steps_per_launch || !host_kernel || !host_tile_w || !host_tile_h)
+    return HLBM_EINVAL;
   *host_steps_per_launch = b->spl;
+  *host_kernel = b->kind;
   *host_tile_w = b->tile_w;
   *host_tile_h = b->tile_h;
   return HLBM_OK;

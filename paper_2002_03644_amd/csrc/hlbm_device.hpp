@@ -278,13 +278,32 @@ struct TileRings {
   real fm[2][W];     // populations 7, 8   (c_y = -1)
 };
 
+// Batched items: the skip of a frozen domain is decided once per item for
+// the whole workgroup (another workgroup can set the flag at any moment, and
+// waves that read it at different times would disagree and pair up barriers
+// across items).  Every thread reads the flag word before the item's first
+// loads are issued (one request per wave, no branch, so no wait for it is
+// placed before those loads); the sweep's first barrier, an OR over the
+// threads, then decides for all of them, so the flag's latency overlaps the
+// loads.
+__device__ __forceinline__ unsigned domain_frozen(const unsigned *status) {
+  return __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <bool kBatch>
+__device__ __forceinline__ bool barrier_skip(unsigned frozen) {
+  if constexpr (kBatch) return __syncthreads_or(frozen != 0u) != 0;
+  __syncthreads();
+  return false;
+}
+
 // One tile (bx, by) of one domain: src / dst point at plane 0 of the two
 // state buffers, planes are `d.plane` elements apart.  Ends with a barrier,
-// so the rings can be reused by the next tile.
-template <int CW>
+// so the rings can be reused by the next tile.  kBatch: returns after the
+// prologue when any thread's `frozen` is nonzero (see domain_frozen).
+template <int CW, bool kBatch = false>
 __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0, real *dst0,
                                            unsigned *status, const int rows, const int bx,
-                                           const int by, TileRings<CW> &R) {
+                                           const int by, const unsigned frozen, TileRings<CW> &R) {
   const int t = threadIdx.x;
   const real *src[kPlanes];
   real *dst[kPlanes];
@@ -392,7 +411,7 @@ __device__ __forceinline__ void sweep_tile(const DomainArgs &d, const real *src0
     for (int q = 0; q < kPlanes; ++q) ld[q] = load_at(src[q], off);
     stage_a(0, ld);
   }
-  __syncthreads();
+  if (barrier_skip<kBatch>(frozen)) return;
 
   for (int i = 0; i < nit; ++i) {
     // ---------------- issue the loads of row i+1 (consumed by A after B)
@@ -566,17 +585,13 @@ __global__ __launch_bounds__(CW + 64) void k_step(StepArgs a) {
     const int full = nblk - (per - 1) * 8;  // XCDs that get `per` tiles
     bid = xcd < full ? xcd * per + k : full * per + (xcd - full) * (per - 1) + k;
   }
-  sweep_tile<CW>(a.d, a.src, a.dst, a.status, a.rows, bid % a.nbx, bid / a.nbx, R);
+  sweep_tile<CW>(a.d, a.src, a.dst, a.status, a.rows, bid % a.nbx, bid / a.nbx, 0, R);
 }
 
 // Batched step: a persistent grid walks a list of (domain, tile) items,
 // statically round-robin (no atomics: the launch can be captured and
 // replayed).  Items of a domain whose divergence flag is set are skipped, so
-// a diverged domain freezes while the others go on.  The flag can be set by
-// another workgroup at any moment, so the skip is decided once per item for
-// the whole workgroup (a barrier with an OR over the threads): waves that
-// read the flag at different times would otherwise disagree, and the
-// barriers inside the sweep would then pair up across different items.
+// a diverged domain freezes while the others go on (see domain_frozen).
 struct BatchArgs {
   const DomainArgs *doms;
   const long long *offs;  // element offset of each domain's state in a buffer
@@ -594,14 +609,13 @@ __global__ __launch_bounds__(CW + 64) void k_step_batch(BatchArgs a) {
   for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
     const int4 w = a.items[it];
     const int dm = __builtin_amdgcn_readfirstlane(w.x);
-    // one decision per workgroup; the barrier also keeps the previous item's
-    // last ring reads ahead of this item's first writes
-    const int frozen = threadIdx.x == 0 ? (int)(__atomic_load_n(&a.status[dm], __ATOMIC_RELAXED) != 0u) : 0;
-    if (__syncthreads_or(frozen)) continue;
     const DomainArgs d = a.doms[dm];
     const long long off = a.offs[dm];
-    sweep_tile<CW>(d, a.src_buf + off, a.dst_buf + off, a.status + dm, a.rows,
-                   __builtin_amdgcn_readfirstlane(w.y), __builtin_amdgcn_readfirstlane(w.z), R);
+    // after the loads it must not wait for (memory counters drain in order)
+    const unsigned frozen = domain_frozen(a.status + dm);
+    sweep_tile<CW, true>(d, a.src_buf + off, a.dst_buf + off, a.status + dm, a.rows,
+                         __builtin_amdgcn_readfirstlane(w.y), __builtin_amdgcn_readfirstlane(w.z),
+                         frozen, R);
   }
 }
 
@@ -609,6 +623,7 @@ __global__ __launch_bounds__(CW + 64) void k_step_batch(BatchArgs a) {
 }  // namespace hlbm
 
 #include "hlbm_step2.hpp"
+#include "hlbm_tile.hpp"
 
 namespace hlbm {
 namespace HLBM_NS {

@@ -2,4 +2,6 @@
 // without floating-point contraction.
 #define HLBM_REAL double
 #define HLBM_NS f64
+// tile shapes of the batched tile kernel that keep two waves per SIMD in FP64
+#define HLBM_TILE_SHAPES(X) X(32, 8) X(32, 16) X(64, 8)
 #include "hlbm_kernels_impl.hpp"

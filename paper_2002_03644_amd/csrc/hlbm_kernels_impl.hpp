@@ -269,6 +269,54 @@ int batch2_blocks_per_cu(int cw) {
   return e == hipSuccess && n > 0 ? n : 1;
 }
 
+// Shapes of the two-dimensional tile kernel (tile_w x tile_h) built for this
+// precision; FP64 keeps the three whose registers and LDS leave at least two
+// waves per SIMD.
+#ifndef HLBM_TILE_SHAPES
+#define HLBM_TILE_SHAPES(X) X(32, 8) X(32, 16) X(64, 8) X(32, 32) X(64, 16)
+#endif
+
+bool tile_shape_supported(int tw, int th) {
+#define HLBM_TILE_HAS(W, H) \
+  if (tw == W && th == H) return true;
+  HLBM_TILE_SHAPES(HLBM_TILE_HAS)
+#undef HLBM_TILE_HAS
+  return false;
+}
+
+hipError_t step_tile_batch(const void *doms, const long long *offs, const void *items,
+                           int nitems, const void *src, void *dst, unsigned *status, int tw,
+                           int th, int grid, hipStream_t st) {
+  BatchArgs a;
+  a.doms = (const DomainArgs *)doms;
+  a.offs = offs;
+  a.items = (const int4 *)items;
+  a.nitems = nitems;
+  a.src_buf = (const real *)src;
+  a.dst_buf = (real *)dst;
+  a.status = status;
+  a.rows = th;
+#define HLBM_TILE_CASE(W, H)                                                             \
+  if (tw == W && th == H) {                                                              \
+    hipLaunchKernelGGL((k_tile_batch<W, H>), dim3(grid), dim3(kTileThreads), 0, st, a); \
+    return hipGetLastError();                                                            \
+  }
+  HLBM_TILE_SHAPES(HLBM_TILE_CASE)
+#undef HLBM_TILE_CASE
+  return hipErrorInvalidValue;
+}
+
+int tile_blocks_per_cu(int tw, int th) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define HLBM_TILE_OCC(W, H)                                                                 \
+  if (tw == W && th == H)                                                                   \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_batch<W, H>, kTileThreads, 0);
+  HLBM_TILE_SHAPES(HLBM_TILE_OCC)
+#undef HLBM_TILE_OCC
+  return e == hipSuccess && n > 0 ? n : 1;
+}
+
 hipError_t correct(const void *doms, const long long *offs, int count, long long n, void *state,
                    const float *x, const float *dl, double *partials, int conserve,
                    hipStream_t st) {

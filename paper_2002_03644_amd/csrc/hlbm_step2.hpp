@@ -248,10 +248,11 @@ __device__ __forceinline__ void level_advance(LevelRegs &g) {
   g.cB_f0 = g.nB_f0;
 }
 
-template <int CW>
+template <int CW, bool kBatch = false>
 __device__ __forceinline__ void sweep_tile2(const DomainArgs &d, const real *src0, real *dst0,
                                             unsigned *status, const int rows, const int bx,
-                                            const int by, TileRings2<CW> &R) {
+                                            const int by, const unsigned frozen,
+                                            TileRings2<CW> &R) {
   const int t = threadIdx.x;
   const real *src[kPlanes];
   real *dst[kPlanes];
@@ -288,7 +289,7 @@ __device__ __forceinline__ void sweep_tile2(const DomainArgs &d, const real *src
     for (int q = 0; q < kQ; ++q) F[q] = load_at(src[q], off);
     level_a(d, g1, R.L1, 0, ri, F, load_at(src[9], off), bad);
   }
-  __syncthreads();
+  if (barrier_skip<kBatch>(frozen)) return;
 
   for (int i = 0; i < nit; ++i) {
     // ---------------- loads of row i + 1 (consumed by A1 after the B stages)
@@ -344,7 +345,7 @@ __global__ __launch_bounds__(step2_threads(CW)) void k_step2(StepArgs a) {
     const int full = nblk - (per - 1) * 8;
     bid = xcd < full ? xcd * per + k : full * per + (xcd - full) * (per - 1) + k;
   }
-  sweep_tile2<CW>(a.d, a.src, a.dst, a.status, a.rows, bid % a.nbx, bid / a.nbx, R);
+  sweep_tile2<CW>(a.d, a.src, a.dst, a.status, a.rows, bid % a.nbx, bid / a.nbx, 0, R);
 }
 
 // Two steps of a batch of periodic domains: the persistent walk over (domain,
@@ -355,14 +356,13 @@ __global__ __launch_bounds__(step2_threads(CW)) void k_step_batch2(BatchArgs a) 
   for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
     const int4 w = a.items[it];
     const int dm = __builtin_amdgcn_readfirstlane(w.x);
-    // one skip decision per workgroup (see k_step_batch)
-    const int frozen =
-        threadIdx.x == 0 ? (int)(__atomic_load_n(&a.status[dm], __ATOMIC_RELAXED) != 0u) : 0;
-    if (__syncthreads_or(frozen)) continue;
     const DomainArgs d = a.doms[dm];
     const long long off = a.offs[dm];
-    sweep_tile2<CW>(d, a.src_buf + off, a.dst_buf + off, a.status + dm, a.rows,
-                    __builtin_amdgcn_readfirstlane(w.y), __builtin_amdgcn_readfirstlane(w.z), R);
+    // after the loads it must not wait for (memory counters drain in order)
+    const unsigned frozen = domain_frozen(a.status + dm);
+    sweep_tile2<CW, true>(d, a.src_buf + off, a.dst_buf + off, a.status + dm, a.rows,
+                          __builtin_amdgcn_readfirstlane(w.y),
+                          __builtin_amdgcn_readfirstlane(w.z), frozen, R);
   }
 }
 

@@ -184,15 +184,19 @@ def test_autotune_restores_state_and_caches(tmp_path):
     B.step(4)
     before = [m["rho"].clone() for m in B.moments()]
     cache = str(tmp_path / "tune.json")
-    w, h = B.autotune(steps=2, cache_path=cache)
-    assert w in (64, 128, 192, 256) and h in (4, 8, 16, 32, 64, 128)
+    kern, w, h = B.autotune(steps=2, cache_path=cache)
+    if kern == "strips":
+        assert w in (64, 128, 192, 256) and h in (4, 8, 16, 32, 64, 128)
+    else:
+        assert kern == "tiles" and (w, h) in ((32, 8), (32, 16), (64, 8), (32, 32), (64, 16))
+    assert B.plan()[1:] == (kern, w, h)
     after = [m["rho"] for m in B.moments()]
     assert B.steps == 4 and B.status()[0] == 0
     for a, b in zip(before, after):
         assert torch.equal(a, b)
     with open(cache) as fh:
-        assert json.load(fh)[B.signature()] == [w, h]
-    assert B.autotune(cache_path=cache) == (w, h)   # served from the cache
+        assert json.load(fh)[B.signature()] == [kern, w, h]
+    assert B.autotune(cache_path=cache) == (kern, w, h)   # served from the cache
 
 
 def test_batch_256_domains_seed0():
