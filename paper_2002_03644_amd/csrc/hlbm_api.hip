@@ -609,7 +609,11 @@ hipError_t batch_upload_items(hlbm_batch *b, int kind, int tw, int th, hipStream
   b->kind = kind;
   b->tile_w = tw;
   b->tile_h = th;
-  b->spl = kind == HLBM_BATCH_TILES ? 1 : b->spl_strips;
+  const bool tile2 = b->dtype == HLBM_F64 ? hlbm::f64::tile2_shape_supported(tw, th)
+                                           : hlbm::f32::tile2_shape_supported(tw, th);
+  // the tile kernel takes two steps per launch where the strips would and a
+  // two-step tile kernel of this shape exists
+  b->spl = kind == HLBM_BATCH_TILES ? (b->spl_strips == 2 && tile2 ? 2 : 1) : b->spl_strips;
   int per_cu1;
   if (kind == HLBM_BATCH_TILES)
     per_cu1 = b->dtype == HLBM_F64 ? hlbm::f64::tile_blocks_per_cu(tw, th)
@@ -620,8 +624,13 @@ hipError_t batch_upload_items(hlbm_batch *b, int kind, int tw, int th, hipStream
   b->grid1 = std::max(1, std::min(b->nitems, per_cu1 * b->ncu));
   b->grid = b->grid1;
   if (b->spl == 2) {
-    const int per_cu2 = b->dtype == HLBM_F64 ? hlbm::f64::batch2_blocks_per_cu(tw)
-                                             : hlbm::f32::batch2_blocks_per_cu(tw);
+    int per_cu2;
+    if (kind == HLBM_BATCH_TILES)
+      per_cu2 = b->dtype == HLBM_F64 ? hlbm::f64::tile2_blocks_per_cu(tw, th)
+                                     : hlbm::f32::tile2_blocks_per_cu(tw, th);
+    else
+      per_cu2 = b->dtype == HLBM_F64 ? hlbm::f64::batch2_blocks_per_cu(tw)
+                                     : hlbm::f32::batch2_blocks_per_cu(tw);
     b->grid = std::max(1, std::min(b->nitems, per_cu2 * b->ncu));
   }
   for (hipGraphExec_t &g : b->graph) {
@@ -682,7 +691,14 @@ hipError_t batch_launch_spl(hlbm_batch *b, int from, int spl, hipStream_t st) {
   unsigned *stat = (unsigned *)(b->ws + b->off_stat);
   const void *items = b->ws + b->off_items;
   const void *doms = b->ws + b->off_doms;
-  if (b->kind == HLBM_BATCH_TILES) {  // one step per launch
+  if (b->kind == HLBM_BATCH_TILES && spl == 2) {
+    if (b->dtype == HLBM_F64)
+      return hlbm::f64::step_tile_batch2(doms, offs, items, b->nitems, src, dst, stat,
+                                         b->tile_w, b->tile_h, b->grid, st);
+    return hlbm::f32::step_tile_batch2(doms, offs, items, b->nitems, src, dst, stat, b->tile_w,
+                                       b->tile_h, b->grid, st);
+  }
+  if (b->kind == HLBM_BATCH_TILES) {
     if (b->dtype == HLBM_F64)
       return hlbm::f64::step_tile_batch(doms, offs, items, b->nitems, src, dst, stat, b->tile_w,
                                         b->tile_h, b->grid1, st);

@@ -276,6 +276,53 @@ int batch2_blocks_per_cu(int cw) {
 #define HLBM_TILE_SHAPES(X) X(32, 8) X(32, 16) X(64, 8) X(32, 32) X(64, 16)
 #endif
 
+// Shapes of the two-step tile kernel (FP32 only: its registers leave FP64
+// one wave per SIMD).
+#ifndef HLBM_TILE2_SHAPES
+#define HLBM_TILE2_SHAPES(X) X(32, 16)
+#endif
+
+bool tile2_shape_supported(int tw, int th) {
+#define HLBM_TILE_HAS(W, H) \
+  if (tw == W && th == H) return true;
+  HLBM_TILE2_SHAPES(HLBM_TILE_HAS)
+#undef HLBM_TILE_HAS
+  return false;
+}
+
+hipError_t step_tile_batch2(const void *doms, const long long *offs, const void *items,
+                            int nitems, const void *src, void *dst, unsigned *status, int tw,
+                            int th, int grid, hipStream_t st) {
+  BatchArgs a;
+  a.doms = (const DomainArgs *)doms;
+  a.offs = offs;
+  a.items = (const int4 *)items;
+  a.nitems = nitems;
+  a.src_buf = (const real *)src;
+  a.dst_buf = (real *)dst;
+  a.status = status;
+  a.rows = th;
+#define HLBM_TILE_CASE(W, H)                                                              \
+  if (tw == W && th == H) {                                                               \
+    hipLaunchKernelGGL((k_tile_batch2<W, H>), dim3(grid), dim3(kTileThreads), 0, st, a); \
+    return hipGetLastError();                                                             \
+  }
+  HLBM_TILE2_SHAPES(HLBM_TILE_CASE)
+#undef HLBM_TILE_CASE
+  return hipErrorInvalidValue;
+}
+
+int tile2_blocks_per_cu(int tw, int th) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define HLBM_TILE_OCC(W, H)                                                                  \
+  if (tw == W && th == H)                                                                    \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_batch2<W, H>, kTileThreads, 0);
+  HLBM_TILE2_SHAPES(HLBM_TILE_OCC)
+#undef HLBM_TILE_OCC
+  return e == hipSuccess && n > 0 ? n : 1;
+}
+
 bool tile_shape_supported(int tw, int th) {
 #define HLBM_TILE_HAS(W, H) \
   if (tw == W && th == H) return true;

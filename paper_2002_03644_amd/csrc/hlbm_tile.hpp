@@ -1,27 +1,34 @@
-// One step on two-dimensional tiles, for batches of small domains (included
-// by hlbm_device.hpp after the row sweeps).
+// Steps on two-dimensional tiles, for batches of small domains (included by
+// hlbm_device.hpp after the row sweeps).
 //
 // The row sweeps pipeline a strip of rows through the stages; each strip
 // reads rows + 4 input rows and pays a serial fill of the pipeline.  A 256^2
 // domain cut into enough strips to fill the chip has strips of four rows:
 // eight input rows for four output rows, and every wave runs every stage of
-// every row, halo lanes included.  This kernel loads a TW x TH tile and its
-// radius-2 halo at once and runs the stages over the whole tile, with a
-// barrier between them:
+// every row, halo lanes included.  These kernels load a TW x TH tile and its
+// halo at once and run the stages over the whole tile, with a barrier
+// between them:
 //   A  moments of the tile, of the collision ring around it (distance 1)
 //      and of the outer ring (distance 2; its four corners are read by no
 //      stencil and are left out);
 //   B  collision of the tile and of the collision ring: the eight moving
 //      populations into LDS;
-//   C  pull streaming and the entropy update of the tile, stored.
-// Thread t owns tile nodes t, t + 256, ... (row-major, so a wave covers
-// whole row segments and its loads and stores are coalesced) and ring
-// nodes t, t + 256, ... of the ring list (collision ring first).  A node's
-// own moments stay in its owner's registers from A to C; LDS holds only
-// what neighbours read.  The per-node arithmetic is the row sweep's, in the
-// same order, and neighbour indices go through map_index on both axes, so
-// every boundary rule of the row sweep holds and a tile may reach past the
-// domain's edge (nodes outside it are neither updated nor stored).
+//   C  pull streaming and the entropy update of the tile.
+// Thread t owns the slot nodes t, t + 256, ... of the list "tile nodes
+// (row-major, so a wave covers whole row segments and its loads and stores
+// are coalesced), collision ring, outer ring".  A node's own moments stay in
+// its owner's registers from A to C; LDS holds only what neighbours read.
+// The per-node arithmetic is the row sweep's, in the same order, and
+// neighbour indices go through map_index on both axes, so every boundary
+// rule of the row sweep holds and a tile may reach past the domain's edge
+// (nodes outside it are neither updated nor stored).
+//
+// The two-step kernel (domains periodic on both axes, as for the two-step
+// sweep) first runs the three stages on the virtual (TW + 4) x (TH + 4)
+// tile around the output tile, which gives the intermediate state on the
+// radius-2 halo the second step needs, hands that state over through LDS,
+// and runs the stages again on the TW x TH tile: one load and one store of
+// the state per two steps.
 #pragma once
 
 namespace hlbm {
@@ -36,13 +43,12 @@ struct TileGeom {
   static constexpr int NI = TW * TH;                            // tile nodes
   static constexpr int NBR = 2 * (TW + 2) + 2 * TH;             // collision ring
   static constexpr int NAR = 2 * (TW + 2) + 2 * (TH + 2);       // outer ring, corners left out
-  static constexpr int KI = NI / kTileThreads;                  // tile nodes per thread
-  static constexpr int KR = (NBR + NAR + kTileThreads - 1) / kTileThreads;
-  static_assert(NI % kTileThreads == 0, "tile nodes must be a multiple of the workgroup");
+  static constexpr int NS = NI + NBR + NAR;                     // slot nodes
+  static constexpr int K = (NS + kTileThreads - 1) / kTileThreads;  // slots per thread
 };
 
-// LDS of one tile.  Moments arrays are indexed (y + 2) AW + (x + 2) in tile
-// coordinates (x, y), populations (y + 1) BW + (x + 1).
+// LDS of one tile step.  Moments arrays are indexed (y + 2) AW + (x + 2) in
+// tile coordinates (x, y), populations (y + 1) BW + (x + 1).
 template <int TW, int TH>
 struct TileLDS {
   using G = TileGeom<TW, TH>;
@@ -80,60 +86,71 @@ __device__ __forceinline__ void ring_node(int r, int &x, int &y) {
   }
 }
 
+// The slots of one thread (item-independent).
+template <int TW, int TH>
+struct TileSlots {
+  static constexpr int K = TileGeom<TW, TH>::K;
+  int px[K], py[K];  // tile coordinates of each slot's node
+  bool live[K];      // a node of the list (moments)
+  bool coll[K];      // a tile or collision-ring node (collision)
+  bool tile[K];      // a tile node (streaming and entropy)
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ TileSlots<TW, TH> tile_slots(const int t) {
+  using G = TileGeom<TW, TH>;
+  TileSlots<TW, TH> S;
+#pragma unroll
+  for (int k = 0; k < S.K; ++k) {
+    const int g = t + k * kTileThreads;
+    // slots wholly inside one part of the list fold to constants
+    const bool all_tile = (k + 1) * kTileThreads <= G::NI;
+    S.live[k] = (k + 1) * kTileThreads <= G::NS || g < G::NS;
+    S.coll[k] = (k + 1) * kTileThreads <= G::NI + G::NBR || g < G::NI + G::NBR;
+    S.tile[k] = all_tile || g < G::NI;
+    if (all_tile || g < G::NI) {
+      S.py[k] = g / TW;
+      S.px[k] = g - S.py[k] * TW;
+    } else {
+      ring_node<TW, TH>(g < G::NS ? g - G::NI : 0, S.px[k], S.py[k]);
+    }
+  }
+  return S;
+}
+
 // Moments of one node kept by its owner from A to B and C.
 struct TileNode {
   real dr, rho, pxx, pyy, pxy, ux, uy, th, sv;
 };
 
-// One tile (tx, ty) of one domain; returns once its loads are issued when
-// any thread's `frozen` is nonzero (see domain_frozen).  The first barrier, after
-// the loads are issued, also keeps the previous item's LDS reads ahead of
-// this item's writes.
+// Issue the ten loads of every live slot of the tile at (x0, y0).
 template <int TW, int TH>
-__device__ __forceinline__ void tile_step(const DomainArgs &d, const real *src0, real *dst0,
-                                          unsigned *status, const int tx, const int ty,
-                                          const unsigned frozen, TileLDS<TW, TH> &L) {
-  using G = TileGeom<TW, TH>;
-  constexpr int K = G::KI + G::KR;
+__device__ __forceinline__ void tile_loads(const DomainArgs &d, const real *src0, const int x0,
+                                           const int y0, const TileSlots<TW, TH> &S,
+                                           real (&ld)[TileGeom<TW, TH>::K][kPlanes]) {
   constexpr unsigned kEl = sizeof(real);
-  const int t = threadIdx.x;
-  const int x0 = tx * TW, y0 = ty * TH;
-  unsigned bad = 0;
-
-  // ---------------- node of each slot: tile slots first, then ring slots
-  int px[K], py[K];
-  bool live[K];  // ring slots past the end of the ring list are idle
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    if (k < G::KI) {
-      const int n = t + k * kTileThreads;
-      py[k] = n / TW;
-      px[k] = n - py[k] * TW;
-      live[k] = true;
-    } else {
-      const int r = t + (k - G::KI) * kTileThreads;
-      live[k] = r < G::NBR + G::NAR;
-      ring_node<TW, TH>(live[k] ? r : 0, px[k], py[k]);
-    }
-  }
-
-  // ---------------- A: issue every load, then the moments
-  real ld[K][kPlanes];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    if (live[k]) {
-      const int cx = map_index(x0 + px[k], d.nx, d.bcx);
-      const int cy = map_index(y0 + py[k], d.ny, d.bcy);
+  for (int k = 0; k < S.K; ++k) {
+    if (S.live[k]) {
+      const int cx = map_index(x0 + S.px[k], d.nx, d.bcx);
+      const int cy = map_index(y0 + S.py[k], d.ny, d.bcy);
       const unsigned off = (unsigned)(cy * d.pitch + cx) * kEl;
 #pragma unroll
       for (int q = 0; q < kPlanes; ++q) ld[k][q] = load_at(src0 + (long long)q * d.plane, off);
     }
   }
-  if (barrier_skip<true>(frozen)) return;
-  TileNode own[K];
+}
+
+// A: moments of every live slot from its ten values into LDS and `own`.
+template <int TW, int TH>
+__device__ __forceinline__ void tile_a(const DomainArgs &d, const TileSlots<TW, TH> &S,
+                                       const real (&ld)[TileGeom<TW, TH>::K][kPlanes],
+                                       TileNode (&own)[TileGeom<TW, TH>::K],
+                                       TileLDS<TW, TH> &L, unsigned &bad) {
+  using G = TileGeom<TW, TH>;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    if (!live[k]) continue;
+  for (int k = 0; k < S.K; ++k) {
+    if (!S.live[k]) continue;
     real F[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) F[q] = ld[k][q];
@@ -149,7 +166,7 @@ __device__ __forceinline__ void tile_step(const DomainArgs &d, const real *src0,
       th = node_theta(m.rho, sv, d);
       lap_val = th;
     }
-    const int ia = (py[k] + 2) * G::AW + (px[k] + 2);
+    const int ia = (S.py[k] + 2) * G::AW + (S.px[k] + 2);
     L.ux[ia] = ux;
     L.uy[ia] = uy;
     L.lap[ia] = lap_val;
@@ -159,17 +176,26 @@ __device__ __forceinline__ void tile_step(const DomainArgs &d, const real *src0,
     own[k] = TileNode{m.dr, m.rho, m.pxx, m.pyy, m.pxy, ux, uy, th, sv};
     bad |= (m.rho > real(0) && th > real(0) && __builtin_isfinite(ux + uy + th)) ? 0u : 1u;
   }
-  __syncthreads();
+}
 
-  // ---------------- B: collision of the tile and the collision ring
+// B: collision of the tile and the collision ring; the eight moving
+// populations into LDS, population 0 and Phi into registers.  y0: the
+// tile's row origin (wall rows go by the unwrapped row index, as in the row
+// sweep).
+template <int TW, int TH>
+__device__ __forceinline__ void tile_b(const DomainArgs &d, const int y0,
+                                       const TileSlots<TW, TH> &S,
+                                       const TileNode (&own)[TileGeom<TW, TH>::K],
+                                       TileLDS<TW, TH> &L, real (&keep_f0)[TileGeom<TW, TH>::K],
+                                       real (&keep_phi)[TileGeom<TW, TH>::K]) {
+  using G = TileGeom<TW, TH>;
   const real cs2 = real(kCs2);
   const real cref = cs2 * (d.theta_ref - real(1));
-  real keep_f0[G::KI], keep_phi[G::KI];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    if (k >= G::KI && t + (k - G::KI) * kTileThreads >= G::NBR) continue;
+  for (int k = 0; k < S.K; ++k) {
+    if (!S.coll[k]) continue;
     const TileNode &o = own[k];
-    const int i = (py[k] + 2) * G::AW + (px[k] + 2);
+    const int i = (S.py[k] + 2) * G::AW + (S.px[k] + 2);
     const real rho = o.rho, ux = o.ux, uy = o.uy, th = o.th, dr = o.dr;
     const real uxe = L.ux[i + 1], uxw = L.ux[i - 1];
     const real uye = L.uy[i + 1], uyw = L.uy[i - 1];
@@ -207,9 +233,7 @@ __device__ __forceinline__ void tile_step(const DomainArgs &d, const real *src0,
     const real tp = taub * p;
     const real fdxx = -tp * (dxux - dyuy);
     const real fdxy = -tp * (dyux + dxuy);
-    // wall rows (by their unwrapped row index, as in the row sweep) take the
-    // projected stress alone
-    const int yk = y0 + py[k];
+    const int yk = y0 + S.py[k];
     const bool wall_row = d.bcy == kBcWall && (yk == 0 || yk == d.ny - 1);
     const real sg = wall_row ? real(1) : d.sigma, sg1 = real(1) - sg;
     const real a1xx = sg * prxx + sg1 * fdxx;
@@ -235,61 +259,82 @@ __device__ __forceinline__ void tile_step(const DomainArgs &d, const real *src0,
                            : ruxx * uy * uy + rc * (ux * ux + uy * uy) + drc2 + om * a1xxyy;
     real f[kQ];
     project(dr, rux, ruy, Axx, Axy, Ayy, Axxy, Axyy, Axxyy, f);
-    const int j = (py[k] + 1) * G::BW + (px[k] + 1);
+    const int j = (S.py[k] + 1) * G::BW + (S.px[k] + 1);
 #pragma unroll
     for (int q = 1; q < kQ; ++q) L.f[q - 1][j] = f[q];
-    if (k < G::KI) {
-      real phi;
-      if (d.flags & kFlagPhiFD) {
-        const real aa = dxux - dyuy, bb = dyux + dxuy;
-        phi = d.mu * (aa * aa + bb * bb);
-      } else {
-        phi = -(tau * itaub) * (a1xx * dxux + a1xy * (dyux + dxuy) + a1yy * dyuy);
-      }
-      keep_f0[k < G::KI ? k : 0] = f[0];
-      keep_phi[k < G::KI ? k : 0] = phi;
+    real phi;
+    if (d.flags & kFlagPhiFD) {
+      const real aa = dxux - dyuy, bb = dyux + dxuy;
+      phi = d.mu * (aa * aa + bb * bb);
+    } else {
+      phi = -(tau * itaub) * (a1xx * dxux + a1xy * (dyux + dxuy) + a1yy * dyuy);
     }
+    keep_f0[k] = f[0];
+    keep_phi[k] = phi;
   }
-  __syncthreads();
+}
 
-  // ---------------- C: streaming and entropy of the tile's nodes
+// C of slot k (a tile node): the streamed populations and the new entropy.
+template <int TW, int TH>
+__device__ __forceinline__ void tile_c(const DomainArgs &d, const int k,
+                                       const TileSlots<TW, TH> &S,
+                                       const TileNode (&own)[TileGeom<TW, TH>::K],
+                                       const TileLDS<TW, TH> &L,
+                                       const real (&keep_f0)[TileGeom<TW, TH>::K],
+                                       const real (&keep_phi)[TileGeom<TW, TH>::K],
+                                       real (&Fo)[kQ], real &snew) {
+  using G = TileGeom<TW, TH>;
+  const TileNode &o = own[k];
+  const int j = (S.py[k] + 1) * G::BW + (S.px[k] + 1);
+  const int i = (S.py[k] + 2) * G::AW + (S.px[k] + 2);
+  Fo[0] = keep_f0[k];
+  Fo[1] = L.f[0][j - 1];               // from x - 1
+  Fo[3] = L.f[2][j + 1];               // from x + 1
+  Fo[2] = L.f[1][j - G::BW];           // from y - 1
+  Fo[5] = L.f[4][j - G::BW - 1];       // from (x - 1, y - 1)
+  Fo[6] = L.f[5][j - G::BW + 1];       // from (x + 1, y - 1)
+  Fo[4] = L.f[3][j + G::BW];           // from y + 1
+  Fo[7] = L.f[6][j + G::BW + 1];       // from (x + 1, y + 1)
+  Fo[8] = L.f[7][j + G::BW - 1];       // from (x - 1, y + 1)
+  const real sc = o.sv;
+  const real advx = muscl_term(o.ux, L.s[i - 2], L.s[i - 1], sc, L.s[i + 1], L.s[i + 2]);
+  const real advy = muscl_term(o.uy, L.s[i - 2 * G::AW], L.s[i - G::AW], sc, L.s[i + G::AW],
+                               L.s[i + 2 * G::AW]);
+  const real lap = ((L.lap[i + 1] + L.lap[i - 1]) + (L.lap[i + G::AW] + L.lap[i - G::AW])) -
+                   real(4) * L.lap[i];
+  snew = sc - (advx + advy) + div_fast(d.lambda * lap + keep_phi[k], o.rho * o.th);
+}
+
+// C of every tile slot, stored to the state at dst0 (tile origin x0, y0).
+template <int TW, int TH>
+__device__ __forceinline__ void tile_c_store(const DomainArgs &d, real *dst0, const int x0,
+                                             const int y0, const TileSlots<TW, TH> &S,
+                                             const TileNode (&own)[TileGeom<TW, TH>::K],
+                                             const TileLDS<TW, TH> &L,
+                                             const real (&keep_f0)[TileGeom<TW, TH>::K],
+                                             const real (&keep_phi)[TileGeom<TW, TH>::K]) {
+  constexpr unsigned kEl = sizeof(real);
 #pragma unroll
-  for (int k = 0; k < G::KI; ++k) {
-    const int x = x0 + px[k], y = y0 + py[k];
+  for (int k = 0; k < S.K; ++k) {
+    if (!S.tile[k]) continue;
+    const int x = x0 + S.px[k], y = y0 + S.py[k];
     if (x >= d.nx || y >= d.ny) continue;
-    const TileNode &o = own[k];
-    const int j = (py[k] + 1) * G::BW + (px[k] + 1);
-    const int i = (py[k] + 2) * G::AW + (px[k] + 2);
-    real Fo[kQ];
-    Fo[0] = keep_f0[k];
-    Fo[1] = L.f[0][j - 1];               // from x - 1
-    Fo[3] = L.f[2][j + 1];               // from x + 1
-    Fo[2] = L.f[1][j - G::BW];           // from y - 1
-    Fo[5] = L.f[4][j - G::BW - 1];       // from (x - 1, y - 1)
-    Fo[6] = L.f[5][j - G::BW + 1];       // from (x + 1, y - 1)
-    Fo[4] = L.f[3][j + G::BW];           // from y + 1
-    Fo[7] = L.f[6][j + G::BW + 1];       // from (x + 1, y + 1)
-    Fo[8] = L.f[7][j + G::BW - 1];       // from (x - 1, y + 1)
-    const real sc = o.sv;
-    const real advx = muscl_term(o.ux, L.s[i - 2], L.s[i - 1], sc, L.s[i + 1], L.s[i + 2]);
-    const real advy = muscl_term(o.uy, L.s[i - 2 * G::AW], L.s[i - G::AW], sc, L.s[i + G::AW],
-                                 L.s[i + 2 * G::AW]);
-    const real lap = ((L.lap[i + 1] + L.lap[i - 1]) + (L.lap[i + G::AW] + L.lap[i - G::AW])) -
-                     real(4) * L.lap[i];
-    const real snew = sc - (advx + advy) + div_fast(d.lambda * lap + keep_phi[k], o.rho * o.th);
+    real Fo[kQ], snew;
+    tile_c<TW, TH>(d, k, S, own, L, keep_f0, keep_phi, Fo, snew);
     const unsigned off = (unsigned)(y * d.pitch + x) * kEl;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) store_stream(dst0 + (long long)q * d.plane, off, Fo[q]);
     store_stream(dst0 + 9LL * d.plane, off, snew);
   }
-  if (bad) atomicOr(status, 1u);
 }
 
 // Persistent walk over (domain, tile x, tile y) items with the strip
-// kernels' per-workgroup skip of frozen domains.
+// kernels' per-workgroup skip of frozen domains: one step per launch.
 template <int TW, int TH>
 __global__ __launch_bounds__(kTileThreads) void k_tile_batch(BatchArgs a) {
   __shared__ TileLDS<TW, TH> L;
+  using G = TileGeom<TW, TH>;
+  const TileSlots<TW, TH> S = tile_slots<TW, TH>(threadIdx.x);
   for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
     const int4 w = a.items[it];
     const int dm = __builtin_amdgcn_readfirstlane(w.x);
@@ -297,9 +342,105 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_batch(BatchArgs a) {
     const long long off = a.offs[dm];
     // after the loads it must not wait for (memory counters drain in order)
     const unsigned frozen = domain_frozen(a.status + dm);
-    tile_step<TW, TH>(d, a.src_buf + off, a.dst_buf + off, a.status + dm,
-                      __builtin_amdgcn_readfirstlane(w.y), __builtin_amdgcn_readfirstlane(w.z),
-                      frozen, L);
+    const int x0 = __builtin_amdgcn_readfirstlane(w.y) * TW;
+    const int y0 = __builtin_amdgcn_readfirstlane(w.z) * TH;
+    real ld[G::K][kPlanes];
+    tile_loads<TW, TH>(d, a.src_buf + off, x0, y0, S, ld);
+    // one skip decision per workgroup; the barrier also keeps the previous
+    // item's LDS reads ahead of this item's writes
+    if (barrier_skip<true>(frozen)) continue;
+    TileNode own[G::K];
+    unsigned bad = 0;
+    tile_a<TW, TH>(d, S, ld, own, L, bad);
+    __syncthreads();
+    real keep_f0[G::K], keep_phi[G::K];
+    tile_b<TW, TH>(d, y0, S, own, L, keep_f0, keep_phi);
+    __syncthreads();
+    tile_c_store<TW, TH>(d, a.dst_buf + off, x0, y0, S, own, L, keep_f0, keep_phi);
+    if (bad) atomicOr(a.status + dm, 1u);
+  }
+}
+
+// LDS of the two-step kernel: the first step's arrays, then the hand-over
+// of its results (ten values per node of the virtual tile), then the second
+// step's arrays, each region reused after a barrier.
+template <int TW, int TH>
+union TileLDS2 {
+  TileLDS<TW + 4, TH + 4> l1;
+  real xch[kPlanes][(TW + 4) * (TH + 4)];
+  TileLDS<TW, TH> l2;
+};
+
+// Two steps per launch for domains periodic on both axes: step one on the
+// virtual tile (TW + 4) x (TH + 4) at (x0 - 2, y0 - 2), whose results are
+// exactly the intermediate state on the second step's tile and radius-2
+// halo; step two on the TW x TH tile.
+template <int TW, int TH>
+__global__ __launch_bounds__(kTileThreads) void k_tile_batch2(BatchArgs a) {
+  __shared__ TileLDS2<TW, TH> L;
+  using G1 = TileGeom<TW + 4, TH + 4>;
+  using G2 = TileGeom<TW, TH>;
+  constexpr int VW = TW + 4;  // row length of the hand-over
+  const TileSlots<TW + 4, TH + 4> S1 = tile_slots<TW + 4, TH + 4>(threadIdx.x);
+  const TileSlots<TW, TH> S2 = tile_slots<TW, TH>(threadIdx.x);
+  for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+    const int4 w = a.items[it];
+    const int dm = __builtin_amdgcn_readfirstlane(w.x);
+    const DomainArgs d = a.doms[dm];
+    const long long off = a.offs[dm];
+    const unsigned frozen = domain_frozen(a.status + dm);
+    const int x0 = __builtin_amdgcn_readfirstlane(w.y) * TW;
+    const int y0 = __builtin_amdgcn_readfirstlane(w.z) * TH;
+    unsigned bad = 0;
+    // ---------------- step one on the virtual tile
+    real hand[G1::K][kPlanes];  // its results, by slot
+    {
+      real ld[G1::K][kPlanes];
+      tile_loads<TW + 4, TH + 4>(d, a.src_buf + off, x0 - 2, y0 - 2, S1, ld);
+      if (barrier_skip<true>(frozen)) continue;
+      TileNode own[G1::K];
+      tile_a<TW + 4, TH + 4>(d, S1, ld, own, L.l1, bad);
+      __syncthreads();
+      real keep_f0[G1::K], keep_phi[G1::K];
+      tile_b<TW + 4, TH + 4>(d, y0 - 2, S1, own, L.l1, keep_f0, keep_phi);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < G1::K; ++k) {
+        if (!S1.tile[k]) continue;
+        real Fo[kQ], snew;
+        tile_c<TW + 4, TH + 4>(d, k, S1, own, L.l1, keep_f0, keep_phi, Fo, snew);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) hand[k][q] = Fo[q];
+        hand[k][9] = snew;
+      }
+    }
+    __syncthreads();  // every read of the first step's arrays is done
+#pragma unroll
+    for (int k = 0; k < G1::K; ++k) {
+      if (!S1.tile[k]) continue;
+      const int v = S1.py[k] * VW + S1.px[k];
+#pragma unroll
+      for (int q = 0; q < kPlanes; ++q) L.xch[q][v] = hand[k][q];
+    }
+    __syncthreads();
+    // ---------------- step two on the output tile
+    real ld2[G2::K][kPlanes];
+#pragma unroll
+    for (int k = 0; k < G2::K; ++k) {
+      if (!S2.live[k]) continue;
+      const int v = (S2.py[k] + 2) * VW + (S2.px[k] + 2);
+#pragma unroll
+      for (int q = 0; q < kPlanes; ++q) ld2[k][q] = L.xch[q][v];
+    }
+    __syncthreads();  // the hand-over is read before the second step's arrays overwrite it
+    TileNode own2[G2::K];
+    tile_a<TW, TH>(d, S2, ld2, own2, L.l2, bad);
+    __syncthreads();
+    real keep2_f0[G2::K], keep2_phi[G2::K];
+    tile_b<TW, TH>(d, y0, S2, own2, L.l2, keep2_f0, keep2_phi);
+    __syncthreads();
+    tile_c_store<TW, TH>(d, a.dst_buf + off, x0, y0, S2, own2, L.l2, keep2_f0, keep2_phi);
+    if (bad) atomicOr(a.status + dm, 1u);
   }
 }
 

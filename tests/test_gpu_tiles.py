@@ -253,3 +253,68 @@ def test_tiles_256_domain_batch_sample():
         ms = singles([params[k]], [fields[k]], 20)[0]
         err = scaled_err(mb[k], ms)
         assert max(err.values()) < 2e-5, (k, err)
+
+
+# ------------------------------------------------ two steps per launch (FP32)
+def periodic_set(poison=None, spl=0):
+    params, fields = domain_set("f32", poison=poison)
+    params = [dataclasses.replace(p, bc_x="periodic", bc_y="periodic", steps_per_launch=spl)
+              for p in params]
+    return params, fields
+
+
+@pytest.mark.parametrize("steps", [22, 23])
+def test_two_step_tiles_close_to_one_step_kernel(steps):
+    """All domains periodic: 32 x 16 tiles take two steps per launch (an odd
+    count ends with a one-step tile launch).  Each domain stays within FP32
+    rounding of its single-domain run, and of the same batch on one-step
+    tiles."""
+    params, fields = periodic_set()
+    B = BatchSolver(params, fields)
+    B.set_tile(32, 16, kernel="tiles")
+    assert B.plan() == (2, "tiles", 32, 16)
+    B.step(steps, graph=True)
+    assert B.status()[0] == 0 and B.steps == steps
+    mb = B.moments()
+    p1, _ = periodic_set(spl=1)
+    C = BatchSolver(p1, fields)
+    C.set_tile(32, 16, kernel="tiles")
+    assert C.plan() == (1, "tiles", 32, 16)
+    C.step(steps, graph=True)
+    mc = C.moments()
+    ms = singles(params, fields, steps)
+    same = 0
+    for k in range(len(params)):
+        for ref in (ms[k], mc[k]):
+            err = scaled_err(mb[k], ref)
+            assert max(err.values()) < 2e-5, (k, err)
+        same += all(torch.equal(mb[k][key], mc[k][key]) for key in FIELDS)
+    print(f"two-step tiles: {same} of {len(params)} domains bitwise equal to one-step tiles")
+
+
+def test_two_step_tiles_divergence_and_graph_replays():
+    """A domain that diverges at once is frozen by the two-step tile kernel;
+    graph replays equal an eager run after every call on every healthy
+    domain (a frozen domain keeps whatever its tiles held when each
+    workgroup saw the flag, which depends on timing)."""
+    params, fields = periodic_set(poison=2)
+    keep = [k for k in range(len(params)) if k != 2]
+    A = BatchSolver(params, fields)
+    E = BatchSolver(params, fields)
+    for S in (A, E):
+        S.set_tile(32, 16, kernel="tiles")
+    for rep, n in enumerate((16, 3, 34, 2, 17)):
+        A.step(n, graph=True)
+        E.step(n, graph=False)
+        torch.cuda.synchronize()
+        ma, me = A.moments(), E.moments()
+        for k in keep:
+            for key in FIELDS:
+                assert torch.equal(ma[k][key], me[k][key]), (rep, k, key)
+    bad, flags = A.status()
+    assert bad == 1 and flags[2] == 1 and flags.sum() == 1
+    mb = A.moments()
+    ms = singles([params[k] for k in keep], [fields[k] for k in keep], A.steps)
+    for j, k in enumerate(keep):
+        err = scaled_err(mb[k], ms[j])
+        assert max(err.values()) < 5e-5, (k, err)
