@@ -684,26 +684,32 @@ hipError_t batch_graph(hlbm_batch *b, int which, int pairs, hipStream_t st) {
   return hipSuccess;
 }
 
-hipError_t batch_launch_spl(hlbm_batch *b, int from, int spl, hipStream_t st) {
+// `mom`: with the tile kernels, the moments of the new state as
+// hlbm_batch_moments writes them (rho, u_x, u_y, theta channels of
+// b->nodes values each); nullptr for none.
+hipError_t batch_launch_spl(hlbm_batch *b, int from, int spl, hipStream_t st,
+                            void *mom = nullptr) {
   const char *src = b->ws + (from ? b->off_buf1 : 0);
   char *dst = b->ws + (from ? 0 : b->off_buf1);
   const long long *offs = (const long long *)(b->ws + b->off_offs);
   unsigned *stat = (unsigned *)(b->ws + b->off_stat);
   const void *items = b->ws + b->off_items;
   const void *doms = b->ws + b->off_doms;
+  const long long *foffs = (const long long *)(b->ws + b->off_foffs);
   if (b->kind == HLBM_BATCH_TILES && spl == 2) {
     if (b->dtype == HLBM_F64)
       return hlbm::f64::step_tile_batch2(doms, offs, items, b->nitems, src, dst, stat,
-                                         b->tile_w, b->tile_h, b->grid, st);
+                                         b->tile_w, b->tile_h, b->grid, mom, foffs, b->nodes,
+                                         st);
     return hlbm::f32::step_tile_batch2(doms, offs, items, b->nitems, src, dst, stat, b->tile_w,
-                                       b->tile_h, b->grid, st);
+                                       b->tile_h, b->grid, mom, foffs, b->nodes, st);
   }
   if (b->kind == HLBM_BATCH_TILES) {
     if (b->dtype == HLBM_F64)
       return hlbm::f64::step_tile_batch(doms, offs, items, b->nitems, src, dst, stat, b->tile_w,
-                                        b->tile_h, b->grid1, st);
+                                        b->tile_h, b->grid1, mom, foffs, b->nodes, st);
     return hlbm::f32::step_tile_batch(doms, offs, items, b->nitems, src, dst, stat, b->tile_w,
-                                      b->tile_h, b->grid1, st);
+                                      b->tile_h, b->grid1, mom, foffs, b->nodes, st);
   }
   if (spl == 2) {
     if (b->dtype == HLBM_F64)
@@ -726,14 +732,15 @@ hipError_t batch_launch(hlbm_batch *b, int from, hipStream_t st) {
 
 // `n` steps from buffer b->cur, eagerly: launches of b->spl steps, then a
 // one-step launch for an odd remainder; advances b->cur (not b->steps).
-hipError_t batch_steps_eager(hlbm_batch *b, int n, hipStream_t st) {
+// `mom` (tile kernels only) goes to the last launch (see batch_launch_spl).
+hipError_t batch_steps_eager(hlbm_batch *b, int n, hipStream_t st, void *mom = nullptr) {
   for (; n >= b->spl; n -= b->spl) {
-    hipError_t e = batch_launch(b, b->cur, st);
+    hipError_t e = batch_launch_spl(b, b->cur, b->spl, st, n == b->spl ? mom : nullptr);
     if (e != hipSuccess) return e;
     b->cur ^= 1;
   }
   for (; n > 0; --n) {
-    hipError_t e = batch_launch_spl(b, b->cur, 1, st);
+    hipError_t e = batch_launch_spl(b, b->cur, 1, st, n == 1 ? mom : nullptr);
     if (e != hipSuccess) return e;
     b->cur ^= 1;
   }
@@ -1021,12 +1028,18 @@ hipError_t correct_launch(hlbm_batch *b, const float *x, const float *delta, int
 // `every` plain steps from buffer b->cur, then the network's correction;
 // advances b->cur
 int closure_once(hlbm_batch *b, hlbm_cnn *c, int every, int conserve, hipStream_t st) {
-  if (batch_steps_eager(b, every, st) != hipSuccess) return HLBM_EHIP;
   float *x = hlbm_cnn_io(c, 0), *d = hlbm_cnn_io(c, 1);
   const long long n = (long long)b->params[0].nx * b->params[0].ny;
   const long long N = n * b->count;
-  int rc = hlbm_batch_moments(b, x, x + N, x + 2 * N, nullptr, x + 3 * N, st);
-  if (rc != HLBM_OK) return rc;
+  int rc = HLBM_OK;
+  if (b->kind == HLBM_BATCH_TILES) {
+    // the last step writes the moments (a frozen domain's are not refreshed)
+    if (batch_steps_eager(b, every, st, x) != hipSuccess) return HLBM_EHIP;
+  } else {
+    if (batch_steps_eager(b, every, st) != hipSuccess) return HLBM_EHIP;
+    rc = hlbm_batch_moments(b, x, x + N, x + 2 * N, nullptr, x + 3 * N, st);
+    if (rc != HLBM_OK) return rc;
+  }
   rc = hlbm_cnn_forward(c, x, n, N, nullptr, b->count, d, n, N, st);
   if (rc != HLBM_OK) return rc;
   return correct_launch(b, x, d, conserve, st) == hipSuccess ? HLBM_OK : HLBM_EHIP;

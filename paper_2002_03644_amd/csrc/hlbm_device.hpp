@@ -601,6 +601,12 @@ struct BatchArgs {
   real *dst_buf;
   unsigned *status;       // one word per domain
   int rows;
+  // tile kernels: when set, the moments (rho, u_x, u_y, theta) of the new
+  // state go to mom[c * mom_sc + foffs[domain] + y nx + x], c = 0..3, as
+  // k_batch_moments computes them
+  real *mom;
+  const long long *foffs;
+  long long mom_sc;
 };
 
 template <int CW>

@@ -200,6 +200,9 @@ hipError_t step_batch(const void *doms, const long long *offs, const void *items
   a.dst_buf = (real *)dst;
   a.status = status;
   a.rows = rows;
+  a.mom = nullptr;
+  a.foffs = nullptr;
+  a.mom_sc = 0;
   switch (cw) {
   case 64:
     hipLaunchKernelGGL(k_step_batch<64>, dim3(grid), dim3(64 + 64), 0, st, a);
@@ -231,6 +234,9 @@ hipError_t step_batch2(const void *doms, const long long *offs, const void *item
   a.dst_buf = (real *)dst;
   a.status = status;
   a.rows = rows;
+  a.mom = nullptr;
+  a.foffs = nullptr;
+  a.mom_sc = 0;
 #define HLBM_BATCH2_CASE(CW)                                                                 \
   case CW:                                                                                   \
     hipLaunchKernelGGL(k_step_batch2<CW>, dim3(grid), dim3(step2_threads(CW)), 0, st, a);    \
@@ -292,8 +298,12 @@ bool tile2_shape_supported(int tw, int th) {
 
 hipError_t step_tile_batch2(const void *doms, const long long *offs, const void *items,
                             int nitems, const void *src, void *dst, unsigned *status, int tw,
-                            int th, int grid, hipStream_t st) {
+                            int th, int grid, void *mom, const long long *foffs,
+                            long long mom_sc, hipStream_t st) {
   BatchArgs a;
+  a.mom = (real *)mom;
+  a.foffs = foffs;
+  a.mom_sc = mom_sc;
   a.doms = (const DomainArgs *)doms;
   a.offs = offs;
   a.items = (const int4 *)items;
@@ -333,8 +343,12 @@ bool tile_shape_supported(int tw, int th) {
 
 hipError_t step_tile_batch(const void *doms, const long long *offs, const void *items,
                            int nitems, const void *src, void *dst, unsigned *status, int tw,
-                           int th, int grid, hipStream_t st) {
+                           int th, int grid, void *mom, const long long *foffs,
+                           long long mom_sc, hipStream_t st) {
   BatchArgs a;
+  a.mom = (real *)mom;
+  a.foffs = foffs;
+  a.mom_sc = mom_sc;
   a.doms = (const DomainArgs *)doms;
   a.offs = offs;
   a.items = (const int4 *)items;

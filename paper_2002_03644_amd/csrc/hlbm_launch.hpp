@@ -133,12 +133,14 @@ inline long long plane_stride(int nx, int ny, int elem_size) {
   int batch2_blocks_per_cu(int cw);                                                         \
   hipError_t step_tile_batch(const void *doms, const long long *offs, const void *items,     \
                              int nitems, const void *src, void *dst, unsigned *status,       \
-                             int tw, int th, int grid, hipStream_t st);                      \
+                             int tw, int th, int grid, void *mom, const long long *foffs,    \
+                             long long mom_sc, hipStream_t st);                              \
   int tile_blocks_per_cu(int tw, int th);                                                   \
   bool tile_shape_supported(int tw, int th);                                                \
   hipError_t step_tile_batch2(const void *doms, const long long *offs, const void *items,    \
                               int nitems, const void *src, void *dst, unsigned *status,      \
-                              int tw, int th, int grid, hipStream_t st);                     \
+                              int tw, int th, int grid, void *mom, const long long *foffs,   \
+                              long long mom_sc, hipStream_t st);                             \
   int tile2_blocks_per_cu(int tw, int th);                                                  \
   bool tile2_shape_supported(int tw, int th);                                               \
   hipError_t correct(const void *doms, const long long *offs, int count, long long n,       \

@@ -305,14 +305,17 @@ __device__ __forceinline__ void tile_c(const DomainArgs &d, const int k,
   snew = sc - (advx + advy) + div_fast(d.lambda * lap + keep_phi[k], o.rho * o.th);
 }
 
-// C of every tile slot, stored to the state at dst0 (tile origin x0, y0).
+// C of every tile slot, stored to the state at dst0 (tile origin x0, y0);
+// with `mom` set also the moments of the new state (see BatchArgs), at
+// mom + fo for this domain.
 template <int TW, int TH>
 __device__ __forceinline__ void tile_c_store(const DomainArgs &d, real *dst0, const int x0,
                                              const int y0, const TileSlots<TW, TH> &S,
                                              const TileNode (&own)[TileGeom<TW, TH>::K],
                                              const TileLDS<TW, TH> &L,
                                              const real (&keep_f0)[TileGeom<TW, TH>::K],
-                                             const real (&keep_phi)[TileGeom<TW, TH>::K]) {
+                                             const real (&keep_phi)[TileGeom<TW, TH>::K],
+                                             real *mom, const long long mom_sc) {
   constexpr unsigned kEl = sizeof(real);
 #pragma unroll
   for (int k = 0; k < S.K; ++k) {
@@ -325,6 +328,14 @@ __device__ __forceinline__ void tile_c_store(const DomainArgs &d, real *dst0, co
 #pragma unroll
     for (int q = 0; q < kQ; ++q) store_stream(dst0 + (long long)q * d.plane, off, Fo[q]);
     store_stream(dst0 + 9LL * d.plane, off, snew);
+    if (mom) {  // the arithmetic of k_batch_moments on the values just stored
+      const NodeMoments m = node_moments(Fo, d);
+      const long long i = (long long)y * d.nx + x;
+      mom[i] = m.rho;
+      mom[mom_sc + i] = m.jx / m.rho;
+      mom[2 * mom_sc + i] = m.jy / m.rho;
+      mom[3 * mom_sc + i] = node_theta(m.rho, snew, d);
+    }
   }
 }
 
@@ -356,7 +367,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_batch(BatchArgs a) {
     real keep_f0[G::K], keep_phi[G::K];
     tile_b<TW, TH>(d, y0, S, own, L, keep_f0, keep_phi);
     __syncthreads();
-    tile_c_store<TW, TH>(d, a.dst_buf + off, x0, y0, S, own, L, keep_f0, keep_phi);
+    tile_c_store<TW, TH>(d, a.dst_buf + off, x0, y0, S, own, L, keep_f0, keep_phi,
+                         a.mom ? a.mom + a.foffs[dm] : nullptr, a.mom_sc);
     if (bad) atomicOr(a.status + dm, 1u);
   }
 }
@@ -439,7 +451,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_batch2(BatchArgs a) {
     real keep2_f0[G2::K], keep2_phi[G2::K];
     tile_b<TW, TH>(d, y0, S2, own2, L.l2, keep2_f0, keep2_phi);
     __syncthreads();
-    tile_c_store<TW, TH>(d, a.dst_buf + off, x0, y0, S2, own2, L.l2, keep2_f0, keep2_phi);
+    tile_c_store<TW, TH>(d, a.dst_buf + off, x0, y0, S2, own2, L.l2, keep2_f0, keep2_phi,
+                         a.mom ? a.mom + a.foffs[dm] : nullptr, a.mom_sc);
     if (bad) atomicOr(a.status + dm, 1u);
   }
 }
