@@ -275,11 +275,12 @@ int batch2_blocks_per_cu(int cw) {
   return e == hipSuccess && n > 0 ? n : 1;
 }
 
-// Shapes of the two-dimensional tile kernel (tile_w x tile_h) built for this
-// precision; FP64 keeps the three whose registers and LDS leave at least two
-// waves per SIMD.
+// Shapes of the two-dimensional tile kernel (tile_w x tile_h, workgroup
+// size) built for this precision; FP64 keeps the three whose registers and
+// LDS leave at least two waves per SIMD.  The largest tiles take 512
+// threads: fewer nodes per thread, half the registers, twice the waves.
 #ifndef HLBM_TILE_SHAPES
-#define HLBM_TILE_SHAPES(X) X(32, 8) X(32, 16) X(64, 8) X(32, 32) X(64, 16)
+#define HLBM_TILE_SHAPES(X) X(32, 8, 256) X(32, 16, 256) X(64, 8, 256) X(32, 32, 512) X(64, 16, 512)
 #endif
 
 // Shapes of the two-step tile kernel (FP32 only: its registers leave FP64
@@ -287,6 +288,7 @@ int batch2_blocks_per_cu(int cw) {
 #ifndef HLBM_TILE2_SHAPES
 #define HLBM_TILE2_SHAPES(X) X(32, 16)
 #endif
+constexpr int kTile2Threads = 512;  // workgroup of the two-step tile kernel
 
 bool tile2_shape_supported(int tw, int th) {
 #define HLBM_TILE_HAS(W, H) \
@@ -314,7 +316,8 @@ hipError_t step_tile_batch2(const void *doms, const long long *offs, const void 
   a.rows = th;
 #define HLBM_TILE_CASE(W, H)                                                              \
   if (tw == W && th == H) {                                                               \
-    hipLaunchKernelGGL((k_tile_batch2<W, H>), dim3(grid), dim3(kTileThreads), 0, st, a); \
+    hipLaunchKernelGGL((k_tile_batch2<W, H, kTile2Threads>), dim3(grid), dim3(kTile2Threads), \
+                       0, st, a);                                                         \
     return hipGetLastError();                                                             \
   }
   HLBM_TILE2_SHAPES(HLBM_TILE_CASE)
@@ -327,14 +330,15 @@ int tile2_blocks_per_cu(int tw, int th) {
   hipError_t e = hipErrorInvalidValue;
 #define HLBM_TILE_OCC(W, H)                                                                  \
   if (tw == W && th == H)                                                                    \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_batch2<W, H>, kTileThreads, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_batch2<W, H, kTile2Threads>, \
+                                                     kTile2Threads, 0);
   HLBM_TILE2_SHAPES(HLBM_TILE_OCC)
 #undef HLBM_TILE_OCC
   return e == hipSuccess && n > 0 ? n : 1;
 }
 
 bool tile_shape_supported(int tw, int th) {
-#define HLBM_TILE_HAS(W, H) \
+#define HLBM_TILE_HAS(W, H, NT) \
   if (tw == W && th == H) return true;
   HLBM_TILE_SHAPES(HLBM_TILE_HAS)
 #undef HLBM_TILE_HAS
@@ -357,9 +361,9 @@ hipError_t step_tile_batch(const void *doms, const long long *offs, const void *
   a.dst_buf = (real *)dst;
   a.status = status;
   a.rows = th;
-#define HLBM_TILE_CASE(W, H)                                                             \
+#define HLBM_TILE_CASE(W, H, NT)                                                         \
   if (tw == W && th == H) {                                                              \
-    hipLaunchKernelGGL((k_tile_batch<W, H>), dim3(grid), dim3(kTileThreads), 0, st, a); \
+    hipLaunchKernelGGL((k_tile_batch<W, H, NT>), dim3(grid), dim3(NT), 0, st, a);       \
     return hipGetLastError();                                                            \
   }
   HLBM_TILE_SHAPES(HLBM_TILE_CASE)
@@ -370,9 +374,9 @@ hipError_t step_tile_batch(const void *doms, const long long *offs, const void *
 int tile_blocks_per_cu(int tw, int th) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
-#define HLBM_TILE_OCC(W, H)                                                                 \
+#define HLBM_TILE_OCC(W, H, NT)                                                             \
   if (tw == W && th == H)                                                                   \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_batch<W, H>, kTileThreads, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_batch<W, H, NT>, NT, 0);
   HLBM_TILE_SHAPES(HLBM_TILE_OCC)
 #undef HLBM_TILE_OCC
   return e == hipSuccess && n > 0 ? n : 1;
