@@ -264,10 +264,10 @@ typedef struct hlbm_batch hlbm_batch;
  *   HLBM_BATCH_TILES   tile_w x tile_h tiles whose halo is loaded at once:
  *                      less recomputed halo, for domains too small to give
  *                      long strips.  One step per launch, two for 32 x 16
- *                      tiles when every domain's own plan has two (the
- *                      first step then runs on the tile grown by two nodes
- *                      on every side, which yields the second step's
- *                      halo). */
+ *                      and 64 x 8 tiles when every domain's own plan has
+ *                      two (the first step then runs on the tile grown by
+ *                      two nodes on every side, which yields the second
+ *                      step's halo). */
 typedef enum { HLBM_BATCH_STRIPS = 0, HLBM_BATCH_TILES = 1 } hlbm_batch_kernel;
 
 /* Workspace bytes for `count` domains, or 0 if any parameter set is invalid,

@@ -286,7 +286,7 @@ int batch2_blocks_per_cu(int cw) {
 // Shapes of the two-step tile kernel (FP32 only: its registers leave FP64
 // one wave per SIMD).
 #ifndef HLBM_TILE2_SHAPES
-#define HLBM_TILE2_SHAPES(X) X(32, 16)
+#define HLBM_TILE2_SHAPES(X) X(32, 16) X(64, 8)
 #endif
 constexpr int kTile2Threads = 512;  // workgroup of the two-step tile kernel
 

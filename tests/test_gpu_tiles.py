@@ -263,23 +263,23 @@ def periodic_set(poison=None, spl=0):
     return params, fields
 
 
-@pytest.mark.parametrize("steps", [22, 23])
-def test_two_step_tiles_close_to_one_step_kernel(steps):
-    """All domains periodic: 32 x 16 tiles take two steps per launch (an odd
-    count ends with a one-step tile launch).  Each domain stays within FP32
-    rounding of its single-domain run, and of the same batch on one-step
-    tiles."""
+@pytest.mark.parametrize("tile,steps", [((32, 16), 22), ((32, 16), 23), ((64, 8), 23)])
+def test_two_step_tiles_close_to_one_step_kernel(tile, steps):
+    """All domains periodic: 32 x 16 and 64 x 8 tiles take two steps per
+    launch (an odd count ends with a one-step tile launch).  Each domain
+    stays within FP32 rounding of its single-domain run, and of the same
+    batch on one-step tiles."""
     params, fields = periodic_set()
     B = BatchSolver(params, fields)
-    B.set_tile(32, 16, kernel="tiles")
-    assert B.plan() == (2, "tiles", 32, 16)
+    B.set_tile(*tile, kernel="tiles")
+    assert B.plan() == (2, "tiles") + tile
     B.step(steps, graph=True)
     assert B.status()[0] == 0 and B.steps == steps
     mb = B.moments()
     p1, _ = periodic_set(spl=1)
     C = BatchSolver(p1, fields)
-    C.set_tile(32, 16, kernel="tiles")
-    assert C.plan() == (1, "tiles", 32, 16)
+    C.set_tile(*tile, kernel="tiles")
+    assert C.plan() == (1, "tiles") + tile
     C.step(steps, graph=True)
     mc = C.moments()
     ms = singles(params, fields, steps)
