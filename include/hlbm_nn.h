@@ -130,7 +130,12 @@ int hlbm_batch_correct(hlbm_batch *b, const float *x, const float *delta, int32_
  * hlbm_batch_correct.  The network must have been created for max_batch >=
  * count and the domains' ny x nx, and trained for increments over `every`
  * steps; its workspace holds the moments and increments.  use_graph = 1
- * replays a captured two-cycle hipGraph (stream must not be NULL). */
+ * replays a captured two-cycle hipGraph (stream must not be NULL).  With
+ * the HLBM_BATCH_TILES kernel (hlbm_batch_set_shape) the same results come
+ * with fewer passes over the state: a cycle's last step also writes the
+ * moments, and a cycle's correction is applied by the next cycle's first
+ * step as it loads the state (the last cycle's by a pass of its own before
+ * the call returns); a frozen domain's moments are then not refreshed. */
 int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t ncycles, int32_t every,
                       int32_t conserve, int32_t use_graph, hlbm_stream_t stream);
 

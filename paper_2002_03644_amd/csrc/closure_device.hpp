@@ -61,6 +61,28 @@ __global__ __launch_bounds__(kCorrThreads) void k_corr_sums(CorrArgs a) {
   }
 }
 
+// Total q of domain k over its kCorrParts partial sums, in a fixed order.
+__device__ __forceinline__ double corr_total(const double *partials, int k, int q) {
+  double t = 0.0;
+  for (int j = 0; j < kCorrParts; ++j) t += partials[((long long)k * kCorrParts + j) * kCorrVals + q];
+  return t;
+}
+
+// The domain's conservation shifts a (density) and b (momentum) from its
+// totals (zero when conservation is not asked for), for n nodes.
+struct CorrShift {
+  real sa, bx, by;
+};
+__device__ __forceinline__ CorrShift corr_shift(const double *tot, long long n, int conserve) {
+  const double inv_n = 1.0 / (double)n;
+  const double am = conserve ? tot[0] * inv_n : 0.0;
+  CorrShift c;
+  c.sa = (real)am;
+  c.bx = conserve ? (real)((tot[1] - am * tot[3]) * inv_n) : real(0);
+  c.by = conserve ? (real)((tot[2] - am * tot[4]) * inv_n) : real(0);
+  return c;
+}
+
 // Hermite coefficients of f^eq(rho, u, theta) that the projection needs,
 // c = c_s^2 (theta - 1).
 struct EqCoef {
@@ -83,45 +105,54 @@ __device__ __forceinline__ EqCoef eq_coef(real r, real u, real v, real th) {
   return e;
 }
 
+// The correction of one node: x, dl point at the node's domain in the
+// moments and increments (channel stride sc), i is its dense index; F and
+// sv hold its stored state and receive the corrected one.  Shared by
+// k_corr_apply and the tile kernels, which apply a pending correction to
+// the state they load (identical arithmetic, so identical results).
+__device__ __forceinline__ void corr_node(const DomainArgs &d, const float *x, const float *dl,
+                                          long long sc, long long i, const CorrShift &c,
+                                          real (&F)[kQ], real &sv) {
+  const real r = x[i], u = x[sc + i];
+  const real v = x[2 * sc + i], th = x[3 * sc + i];
+  const real dr = dl[i], du = dl[sc + i];
+  const real dv = dl[2 * sc + i], dth = dl[3 * sc + i];
+  const real r2 = r + dr - c.sa;
+  const real inv_r2 = real(1) / r2;
+  const real u2 = (u + du) - c.bx * inv_r2, v2 = (v + dv) - c.by * inv_r2;
+  const real th2 = th + dth;
+  const EqCoef e1 = eq_coef(r, u, v, th), e2 = eq_coef(r2, u2, v2, th2);
+  real df[kQ];
+  const real dxxyy = (d.flags & kFlagFeq3) ? real(0) : e2.Axxyy - e1.Axxyy;
+  project(e2.A0 - e1.A0, e2.Ax - e1.Ax, e2.Ay - e1.Ay, e2.Axx - e1.Axx, e2.Axy - e1.Axy,
+          e2.Ayy - e1.Ayy, e2.Axxy - e1.Axxy, e2.Axyy - e1.Axyy, dxxyy, df);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) F[q] += df[q];
+  const real cv = real(1) / d.inv_cv;
+  sv += cv * (log_r(th2 / th) - d.gm1 * log_r(r2 / r));
+}
+
 __global__ __launch_bounds__(kCorrThreads) void k_corr_apply(CorrArgs a) {
   __shared__ double tot[kCorrVals];
   const int k = blockIdx.y;
-  if (threadIdx.x < kCorrVals) {
-    double t = 0.0;
-    for (int j = 0; j < kCorrParts; ++j)
-      t += a.partials[((long long)k * kCorrParts + j) * kCorrVals + threadIdx.x];
-    tot[threadIdx.x] = t;
-  }
+  if (threadIdx.x < kCorrVals) tot[threadIdx.x] = corr_total(a.partials, k, threadIdx.x);
   __syncthreads();
   const DomainArgs &d = a.doms[k];
-  const double inv_n = 1.0 / (double)a.n;
-  const double am = a.conserve ? tot[0] * inv_n : 0.0;
-  const real sa = (real)am;
-  const real bx = a.conserve ? (real)((tot[1] - am * tot[3]) * inv_n) : real(0);
-  const real by = a.conserve ? (real)((tot[2] - am * tot[4]) * inv_n) : real(0);
+  const CorrShift c = corr_shift(tot, a.n, a.conserve);
   real *st = a.state + a.offs[k];
   const long long P = d.plane;
   const long long base = (long long)k * a.n;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.n;
        i += (long long)gridDim.x * blockDim.x) {
-    const real r = a.x[base + i], u = a.x[a.sc + base + i];
-    const real v = a.x[2 * a.sc + base + i], th = a.x[3 * a.sc + base + i];
-    const real dr = a.dl[base + i], du = a.dl[a.sc + base + i];
-    const real dv = a.dl[2 * a.sc + base + i], dth = a.dl[3 * a.sc + base + i];
-    const real r2 = r + dr - sa;
-    const real inv_r2 = real(1) / r2;
-    const real u2 = (u + du) - bx * inv_r2, v2 = (v + dv) - by * inv_r2;
-    const real th2 = th + dth;
-    const EqCoef e1 = eq_coef(r, u, v, th), e2 = eq_coef(r2, u2, v2, th2);
-    real df[kQ];
-    const real dxxyy = (d.flags & kFlagFeq3) ? real(0) : e2.Axxyy - e1.Axxyy;
-    project(e2.A0 - e1.A0, e2.Ax - e1.Ax, e2.Ay - e1.Ay, e2.Axx - e1.Axx, e2.Axy - e1.Axy,
-            e2.Ayy - e1.Ayy, e2.Axxy - e1.Axxy, e2.Axyy - e1.Axyy, dxxyy, df);
     const long long o = state_off(d, i);
+    real F[kQ];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) st[q * P + o] += df[q];
-    const real cv = real(1) / d.inv_cv;
-    st[9 * P + o] += cv * (log_r(th2 / th) - d.gm1 * log_r(r2 / r));
+    for (int q = 0; q < kQ; ++q) F[q] = st[q * P + o];
+    real sv = st[9 * P + o];
+    corr_node(d, a.x + base, a.dl + base, a.sc, i, c, F, sv);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) st[q * P + o] = F[q];
+    st[9 * P + o] = sv;
   }
 }
 

@@ -506,6 +506,7 @@ struct hlbm_batch {
   int graph_cur[2] = {-1, -1};
   hipGraphExec_t cgraph = nullptr;    // captured corrected steps (hlbm_closure_step)
   int cgraph_cur = -1, cgraph_conserve = -1, cgraph_version = -1, cgraph_every = -1;
+  int cgraph_pending = -1;  // whether the captured cycles start with a pending correction
   const hlbm_cnn *cgraph_net = nullptr;
 };
 
@@ -688,7 +689,9 @@ hipError_t batch_graph(hlbm_batch *b, int which, int pairs, hipStream_t st) {
 // hlbm_batch_moments writes them (rho, u_x, u_y, theta channels of
 // b->nodes values each); nullptr for none.
 hipError_t batch_launch_spl(hlbm_batch *b, int from, int spl, hipStream_t st,
-                            void *mom = nullptr) {
+                            void *mom = nullptr, const hlbm::TileCorr *corr = nullptr) {
+  const hlbm::TileCorr none;
+  const hlbm::TileCorr &cr = corr ? *corr : none;
   const char *src = b->ws + (from ? b->off_buf1 : 0);
   char *dst = b->ws + (from ? 0 : b->off_buf1);
   const long long *offs = (const long long *)(b->ws + b->off_offs);
@@ -700,16 +703,16 @@ hipError_t batch_launch_spl(hlbm_batch *b, int from, int spl, hipStream_t st,
     if (b->dtype == HLBM_F64)
       return hlbm::f64::step_tile_batch2(doms, offs, items, b->nitems, src, dst, stat,
                                          b->tile_w, b->tile_h, b->grid, mom, foffs, b->nodes,
-                                         st);
+                                         cr, st);
     return hlbm::f32::step_tile_batch2(doms, offs, items, b->nitems, src, dst, stat, b->tile_w,
-                                       b->tile_h, b->grid, mom, foffs, b->nodes, st);
+                                       b->tile_h, b->grid, mom, foffs, b->nodes, cr, st);
   }
   if (b->kind == HLBM_BATCH_TILES) {
     if (b->dtype == HLBM_F64)
       return hlbm::f64::step_tile_batch(doms, offs, items, b->nitems, src, dst, stat, b->tile_w,
-                                        b->tile_h, b->grid1, mom, foffs, b->nodes, st);
+                                        b->tile_h, b->grid1, mom, foffs, b->nodes, cr, st);
     return hlbm::f32::step_tile_batch(doms, offs, items, b->nitems, src, dst, stat, b->tile_w,
-                                      b->tile_h, b->grid1, mom, foffs, b->nodes, st);
+                                      b->tile_h, b->grid1, mom, foffs, b->nodes, cr, st);
   }
   if (spl == 2) {
     if (b->dtype == HLBM_F64)
@@ -732,20 +735,30 @@ hipError_t batch_launch(hlbm_batch *b, int from, hipStream_t st) {
 
 // `n` steps from buffer b->cur, eagerly: launches of b->spl steps, then a
 // one-step launch for an odd remainder; advances b->cur (not b->steps).
-// `mom` (tile kernels only) goes to the last launch (see batch_launch_spl).
-hipError_t batch_steps_eager(hlbm_batch *b, int n, hipStream_t st, void *mom = nullptr) {
+// Tile kernels only: `mom` goes to the last launch, `corr` to the first
+// (see batch_launch_spl).
+hipError_t batch_steps_eager(hlbm_batch *b, int n, hipStream_t st, void *mom = nullptr,
+                             const hlbm::TileCorr *corr = nullptr) {
+  bool first = true;
   for (; n >= b->spl; n -= b->spl) {
-    hipError_t e = batch_launch_spl(b, b->cur, b->spl, st, n == b->spl ? mom : nullptr);
+    hipError_t e = batch_launch_spl(b, b->cur, b->spl, st, n == b->spl ? mom : nullptr,
+                                    first ? corr : nullptr);
     if (e != hipSuccess) return e;
     b->cur ^= 1;
+    first = false;
   }
   for (; n > 0; --n) {
-    hipError_t e = batch_launch_spl(b, b->cur, 1, st, n == 1 ? mom : nullptr);
+    hipError_t e =
+        batch_launch_spl(b, b->cur, 1, st, n == 1 ? mom : nullptr, first ? corr : nullptr);
     if (e != hipSuccess) return e;
     b->cur ^= 1;
+    first = false;
   }
   return hipSuccess;
 }
+
+// Launches batch_steps_eager makes for `n` steps.
+int batch_launch_count(const hlbm_batch *b, int n) { return n / b->spl + n % b->spl; }
 
 }  // namespace
 
@@ -1025,24 +1038,71 @@ hipError_t correct_launch(hlbm_batch *b, const float *x, const float *delta, int
                             conserve, st);
 }
 
-// `every` plain steps from buffer b->cur, then the network's correction;
-// advances b->cur
-int closure_once(hlbm_batch *b, hlbm_cnn *c, int every, int conserve, hipStream_t st) {
+// The application half of correct_launch, on sums already taken.
+hipError_t correct_apply_launch(hlbm_batch *b, const float *x, const float *delta, int conserve,
+                                hipStream_t st) {
+  char *state = b->ws + (b->cur ? b->off_buf1 : 0);
+  const long long n = (long long)b->params[0].nx * b->params[0].ny;
+  return hlbm::f32::correct_apply(b->ws + b->off_doms, (const long long *)(b->ws + b->off_offs),
+                                  b->count, n, state, x, delta,
+                                  (const double *)(b->ws + b->off_corr), conserve, st);
+}
+
+// One corrected cycle: `every` plain steps from buffer b->cur, then the
+// network's correction; advances b->cur.  With the strip kernels the
+// moments and the correction run as passes of their own.  With the tile
+// kernels the cycle's last step writes the moments, and the correction is
+// left pending (its sums taken, the state not yet moved): the next cycle's
+// first step applies it to the state as it loads it (unless that step is
+// also the cycle's last, which overwrites the moments), or closure_flush
+// does.  `pending` says on entry whether the previous cycle left one and on
+// return whether this one did.  A frozen domain's moments are not refreshed
+// and its pending corrections are dropped.
+int closure_once(hlbm_batch *b, hlbm_cnn *c, int every, int conserve, hipStream_t st,
+                 bool &pending) {
   float *x = hlbm_cnn_io(c, 0), *d = hlbm_cnn_io(c, 1);
   const long long n = (long long)b->params[0].nx * b->params[0].ny;
   const long long N = n * b->count;
   int rc = HLBM_OK;
   if (b->kind == HLBM_BATCH_TILES) {
-    // the last step writes the moments (a frozen domain's are not refreshed)
-    if (batch_steps_eager(b, every, st, x) != hipSuccess) return HLBM_EHIP;
-  } else {
-    if (batch_steps_eager(b, every, st) != hipSuccess) return HLBM_EHIP;
-    rc = hlbm_batch_moments(b, x, x + N, x + 2 * N, nullptr, x + 3 * N, st);
+    hlbm::TileCorr corr;
+    if (pending && batch_launch_count(b, every) >= 2) {
+      corr.x = x;
+      corr.dl = d;
+      corr.partials = (const double *)(b->ws + b->off_corr);
+      corr.conserve = conserve;
+    } else if (pending) {
+      if (correct_apply_launch(b, x, d, conserve, st) != hipSuccess) return HLBM_EHIP;
+    }
+    if (batch_steps_eager(b, every, st, x, corr.x ? &corr : nullptr) != hipSuccess)
+      return HLBM_EHIP;
+    rc = hlbm_cnn_forward(c, x, n, N, nullptr, b->count, d, n, N, st);
     if (rc != HLBM_OK) return rc;
+    if (conserve &&
+        hlbm::f32::correct_sums(b->ws + b->off_doms, (const long long *)(b->ws + b->off_offs),
+                                b->count, n, x, d, (double *)(b->ws + b->off_corr),
+                                st) != hipSuccess)
+      return HLBM_EHIP;
+    pending = true;
+    return HLBM_OK;
   }
+  if (batch_steps_eager(b, every, st) != hipSuccess) return HLBM_EHIP;
+  rc = hlbm_batch_moments(b, x, x + N, x + 2 * N, nullptr, x + 3 * N, st);
+  if (rc != HLBM_OK) return rc;
   rc = hlbm_cnn_forward(c, x, n, N, nullptr, b->count, d, n, N, st);
   if (rc != HLBM_OK) return rc;
+  pending = false;
   return correct_launch(b, x, d, conserve, st) == hipSuccess ? HLBM_OK : HLBM_EHIP;
+}
+
+// Apply a correction closure_once left pending.
+int closure_flush(hlbm_batch *b, hlbm_cnn *c, int conserve, hipStream_t st, bool &pending) {
+  if (!pending) return HLBM_OK;
+  pending = false;
+  return correct_apply_launch(b, hlbm_cnn_io(c, 0), hlbm_cnn_io(c, 1), conserve, st) ==
+                 hipSuccess
+             ? HLBM_OK
+             : HLBM_EHIP;
 }
 
 }  // namespace
@@ -1065,11 +1125,21 @@ int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t ncycles, int32_t every
   if (use_graph && !st) return HLBM_EINVAL;
   conserve = conserve ? 1 : 0;
   int n = ncycles;
+  bool pending = false;
+  // the graphs start with a pending correction where the cycles leave one:
+  // the first cycle then runs eagerly
+  const bool fused = b->kind == HLBM_BATCH_TILES;
+  if (use_graph && fused && n >= 3) {
+    const int rc = closure_once(b, c, every, conserve, st, pending);
+    if (rc != HLBM_OK) return rc;
+    b->steps += every;
+    --n;
+  }
   if (use_graph && n >= 2) {
     // two cycles per graph: the state returns to the same buffer
     if (!b->cgraph || b->cgraph_cur != b->cur || b->cgraph_net != c ||
         b->cgraph_conserve != conserve || b->cgraph_version != hlbm_cnn_version(c) ||
-        b->cgraph_every != every) {
+        b->cgraph_every != every || b->cgraph_pending != (int)pending) {
       if (b->cgraph) {
         (void)hipGraphExecDestroy(b->cgraph);
         b->cgraph = nullptr;
@@ -1078,8 +1148,9 @@ int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t ncycles, int32_t every
       hipGraph_t g = nullptr;
       if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return HLBM_EHIP;
-      int rc1 = closure_once(b, c, every, conserve, st);
-      int rc2 = rc1 == HLBM_OK ? closure_once(b, c, every, conserve, st) : rc1;
+      bool gp = pending;
+      int rc1 = closure_once(b, c, every, conserve, st, gp);
+      int rc2 = rc1 == HLBM_OK ? closure_once(b, c, every, conserve, st, gp) : rc1;
       hipError_t e = hipStreamEndCapture(st, &g);
       b->cur = cur0;   // capture only recorded the launches
       if (rc1 != HLBM_OK || rc2 != HLBM_OK || e != hipSuccess) {
@@ -1097,18 +1168,20 @@ int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t ncycles, int32_t every
       b->cgraph_conserve = conserve;
       b->cgraph_version = hlbm_cnn_version(c);
       b->cgraph_every = every;
+      b->cgraph_pending = (int)pending;
     }
     for (; n >= 2; n -= 2) {
       if (hipGraphLaunch(b->cgraph, st) != hipSuccess) return HLBM_EHIP;
       b->steps += 2 * every;
+      pending = fused;  // a replayed cycle leaves a correction pending as an eager one does
     }
   }
   for (; n > 0; --n) {
-    const int rc = closure_once(b, c, every, conserve, st);
+    const int rc = closure_once(b, c, every, conserve, st, pending);
     if (rc != HLBM_OK) return rc;
     b->steps += every;
   }
-  return HLBM_OK;
+  return closure_flush(b, c, conserve, st, pending);
 }
 
 }  // extern "C"

@@ -607,6 +607,13 @@ struct BatchArgs {
   real *mom;
   const long long *foffs;
   long long mom_sc;
+  // tile kernels: when set, a pending learned correction (moments cx,
+  // increments cdl, channel stride mom_sc, per-domain partial sums cparts;
+  // see k_corr_apply) is applied to the state as it is loaded, as
+  // k_corr_apply would have stored it
+  const float *cx, *cdl;
+  const double *cparts;
+  int cconserve;
 };
 
 template <int CW>
@@ -629,6 +636,7 @@ __global__ __launch_bounds__(CW + 64) void k_step_batch(BatchArgs a) {
 }  // namespace hlbm
 
 #include "hlbm_step2.hpp"
+#include "closure_device.hpp"  // the per-node correction the tile kernels can apply
 #include "hlbm_tile.hpp"
 
 namespace hlbm {

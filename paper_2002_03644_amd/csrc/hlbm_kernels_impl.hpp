@@ -203,6 +203,9 @@ hipError_t step_batch(const void *doms, const long long *offs, const void *items
   a.mom = nullptr;
   a.foffs = nullptr;
   a.mom_sc = 0;
+  a.cx = a.cdl = nullptr;
+  a.cparts = nullptr;
+  a.cconserve = 0;
   switch (cw) {
   case 64:
     hipLaunchKernelGGL(k_step_batch<64>, dim3(grid), dim3(64 + 64), 0, st, a);
@@ -237,6 +240,9 @@ hipError_t step_batch2(const void *doms, const long long *offs, const void *item
   a.mom = nullptr;
   a.foffs = nullptr;
   a.mom_sc = 0;
+  a.cx = a.cdl = nullptr;
+  a.cparts = nullptr;
+  a.cconserve = 0;
 #define HLBM_BATCH2_CASE(CW)                                                                 \
   case CW:                                                                                   \
     hipLaunchKernelGGL(k_step_batch2<CW>, dim3(grid), dim3(step2_threads(CW)), 0, st, a);    \
@@ -301,11 +307,15 @@ bool tile2_shape_supported(int tw, int th) {
 hipError_t step_tile_batch2(const void *doms, const long long *offs, const void *items,
                             int nitems, const void *src, void *dst, unsigned *status, int tw,
                             int th, int grid, void *mom, const long long *foffs,
-                            long long mom_sc, hipStream_t st) {
+                            long long mom_sc, const TileCorr &corr, hipStream_t st) {
   BatchArgs a;
   a.mom = (real *)mom;
   a.foffs = foffs;
   a.mom_sc = mom_sc;
+  a.cx = corr.x;
+  a.cdl = corr.dl;
+  a.cparts = corr.partials;
+  a.cconserve = corr.conserve;
   a.doms = (const DomainArgs *)doms;
   a.offs = offs;
   a.items = (const int4 *)items;
@@ -348,11 +358,15 @@ bool tile_shape_supported(int tw, int th) {
 hipError_t step_tile_batch(const void *doms, const long long *offs, const void *items,
                            int nitems, const void *src, void *dst, unsigned *status, int tw,
                            int th, int grid, void *mom, const long long *foffs,
-                           long long mom_sc, hipStream_t st) {
+                           long long mom_sc, const TileCorr &corr, hipStream_t st) {
   BatchArgs a;
   a.mom = (real *)mom;
   a.foffs = foffs;
   a.mom_sc = mom_sc;
+  a.cx = corr.x;
+  a.cdl = corr.dl;
+  a.cparts = corr.partials;
+  a.cconserve = corr.conserve;
   a.doms = (const DomainArgs *)doms;
   a.offs = offs;
   a.items = (const int4 *)items;
@@ -382,9 +396,9 @@ int tile_blocks_per_cu(int tw, int th) {
   return e == hipSuccess && n > 0 ? n : 1;
 }
 
-hipError_t correct(const void *doms, const long long *offs, int count, long long n, void *state,
-                   const float *x, const float *dl, double *partials, int conserve,
-                   hipStream_t st) {
+static CorrArgs corr_args(const void *doms, const long long *offs, int count, long long n,
+                          void *state, const float *x, const float *dl, const double *partials,
+                          int conserve) {
   CorrArgs a;
   a.doms = (const DomainArgs *)doms;
   a.offs = offs;
@@ -393,14 +407,36 @@ hipError_t correct(const void *doms, const long long *offs, int count, long long
   a.dl = dl;
   a.n = n;
   a.sc = n * count;
-  a.partials = partials;
+  a.partials = (double *)partials;
   a.conserve = conserve;
-  if (conserve)
-    hipLaunchKernelGGL(k_corr_sums, dim3(kCorrParts, count), dim3(kCorrThreads), 0, st, a);
+  return a;
+}
+
+hipError_t correct_sums(const void *doms, const long long *offs, int count, long long n,
+                        const float *x, const float *dl, double *partials, hipStream_t st) {
+  const CorrArgs a = corr_args(doms, offs, count, n, nullptr, x, dl, partials, 1);
+  hipLaunchKernelGGL(k_corr_sums, dim3(kCorrParts, count), dim3(kCorrThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t correct_apply(const void *doms, const long long *offs, int count, long long n,
+                         void *state, const float *x, const float *dl, const double *partials,
+                         int conserve, hipStream_t st) {
+  const CorrArgs a = corr_args(doms, offs, count, n, state, x, dl, partials, conserve);
   const long long per = (n + kCorrThreads - 1) / kCorrThreads;
   const int gx = (int)(per < 256 ? per : 256);
   hipLaunchKernelGGL(k_corr_apply, dim3(gx, count), dim3(kCorrThreads), 0, st, a);
   return hipGetLastError();
+}
+
+hipError_t correct(const void *doms, const long long *offs, int count, long long n, void *state,
+                   const float *x, const float *dl, double *partials, int conserve,
+                   hipStream_t st) {
+  if (conserve) {
+    const hipError_t e = correct_sums(doms, offs, count, n, x, dl, partials, st);
+    if (e != hipSuccess) return e;
+  }
+  return correct_apply(doms, offs, count, n, state, x, dl, partials, conserve, st);
 }
 
 hipError_t batch_moments(const void *doms, const long long *offs, const long long *foffs,

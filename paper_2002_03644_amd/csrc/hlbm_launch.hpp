@@ -104,6 +104,15 @@ inline long long plane_stride(int nx, int ny, int elem_size) {
   return (long long)(bytes / es);
 }
 
+// A pending learned correction for the tile kernels to apply as they load
+// the state (x == nullptr: none): the moments and increments the
+// correction kernels take, and the partial sums of correct_sums.
+struct TileCorr {
+  const float *x = nullptr, *dl = nullptr;
+  const double *partials = nullptr;
+  int conserve = 0;
+};
+
 #define HLBM_DECLARE_LAUNCHERS(NS)                                                          \
   namespace NS {                                                                            \
   hipError_t step(const HostDomain &d, const void *src, void *dst, unsigned *status,        \
@@ -134,19 +143,24 @@ inline long long plane_stride(int nx, int ny, int elem_size) {
   hipError_t step_tile_batch(const void *doms, const long long *offs, const void *items,     \
                              int nitems, const void *src, void *dst, unsigned *status,       \
                              int tw, int th, int grid, void *mom, const long long *foffs,    \
-                             long long mom_sc, hipStream_t st);                              \
+                             long long mom_sc, const TileCorr &corr, hipStream_t st);        \
   int tile_blocks_per_cu(int tw, int th);                                                   \
   bool tile_shape_supported(int tw, int th);                                                \
   hipError_t step_tile_batch2(const void *doms, const long long *offs, const void *items,    \
                               int nitems, const void *src, void *dst, unsigned *status,      \
                               int tw, int th, int grid, void *mom, const long long *foffs,   \
-                              long long mom_sc, hipStream_t st);                             \
+                              long long mom_sc, const TileCorr &corr, hipStream_t st);       \
   int tile2_blocks_per_cu(int tw, int th);                                                  \
   bool tile2_shape_supported(int tw, int th);                                               \
   hipError_t correct(const void *doms, const long long *offs, int count, long long n,       \
                      void *state, const float *x, const float *dl, double *partials,        \
                      int conserve, hipStream_t st);                                         \
   size_t correct_partials_bytes(int count);                                                 \
+  hipError_t correct_sums(const void *doms, const long long *offs, int count, long long n,  \
+                          const float *x, const float *dl, double *partials, hipStream_t st); \
+  hipError_t correct_apply(const void *doms, const long long *offs, int count, long long n, \
+                           void *state, const float *x, const float *dl,                   \
+                           const double *partials, int conserve, hipStream_t st);          \
   hipError_t batch_moments(const void *doms, const long long *offs, const long long *foffs, \
                            int count, long long maxn, const void *state, void *rho, void *ux,  \
                            void *uy, void *s, void *theta, hipStream_t st);                  \

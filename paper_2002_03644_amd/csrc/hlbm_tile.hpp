@@ -143,6 +143,30 @@ __device__ __forceinline__ void tile_loads(const DomainArgs &d, const real *src0
   }
 }
 
+// The pending correction (see BatchArgs) of every live slot's loaded state;
+// dm: the domain, c: its conservation shifts.
+template <int TW, int TH, int NT>
+__device__ __forceinline__ void tile_correct(const DomainArgs &d, const BatchArgs &a, const int dm,
+                                             const CorrShift &c, const int x0, const int y0,
+                                             const TileSlots<TW, TH, NT> &S,
+                                             real (&ld)[TileGeom<TW, TH, NT>::K][kPlanes]) {
+  const long long fo = a.foffs[dm];
+#pragma unroll
+  for (int k = 0; k < S.K; ++k) {
+    if (!S.live[k]) continue;
+    const int cx = map_index(x0 + S.px[k], d.nx, d.bcx);
+    const int cy = map_index(y0 + S.py[k], d.ny, d.bcy);
+    real F[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) F[q] = ld[k][q];
+    real sv = ld[k][9];
+    corr_node(d, a.cx + fo, a.cdl + fo, a.mom_sc, (long long)cy * d.nx + cx, c, F, sv);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) ld[k][q] = F[q];
+    ld[k][9] = sv;
+  }
+}
+
 // A: moments of every live slot from its ten values into LDS and `own`.
 template <int TW, int TH, int NT>
 __device__ __forceinline__ void tile_a(const DomainArgs &d, const TileSlots<TW, TH, NT> &S,
@@ -346,6 +370,7 @@ __device__ __forceinline__ void tile_c_store(const DomainArgs &d, real *dst0, co
 template <int TW, int TH, int NT>
 __global__ __launch_bounds__(NT) void k_tile_batch(BatchArgs a) {
   __shared__ TileLDS<TW, TH> L;
+  __shared__ double ctot[kCorrVals];  // a pending correction's totals
   using G = TileGeom<TW, TH, NT>;
   const TileSlots<TW, TH, NT> S = tile_slots<TW, TH, NT>(threadIdx.x);
   for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
@@ -359,9 +384,14 @@ __global__ __launch_bounds__(NT) void k_tile_batch(BatchArgs a) {
     const int y0 = __builtin_amdgcn_readfirstlane(w.z) * TH;
     real ld[G::K][kPlanes];
     tile_loads<TW, TH>(d, a.src_buf + off, x0, y0, S, ld);
+    if (a.cx && a.cconserve && threadIdx.x < kCorrVals)
+      ctot[threadIdx.x] = corr_total(a.cparts, dm, threadIdx.x);
     // one skip decision per workgroup; the barrier also keeps the previous
-    // item's LDS reads ahead of this item's writes
+    // item's LDS reads ahead of this item's writes, and publishes ctot
     if (barrier_skip<true>(frozen)) continue;
+    if (a.cx)
+      tile_correct<TW, TH>(d, a, dm, corr_shift(ctot, (long long)d.nx * d.ny, a.cconserve), x0,
+                           y0, S, ld);
     TileNode own[G::K];
     unsigned bad = 0;
     tile_a<TW, TH>(d, S, ld, own, L, bad);
@@ -392,6 +422,7 @@ union TileLDS2 {
 template <int TW, int TH, int NT>
 __global__ __launch_bounds__(NT) void k_tile_batch2(BatchArgs a) {
   __shared__ TileLDS2<TW, TH> L;
+  __shared__ double ctot[kCorrVals];  // a pending correction's totals
   using G1 = TileGeom<TW + 4, TH + 4, NT>;
   using G2 = TileGeom<TW, TH, NT>;
   constexpr int VW = TW + 4;  // row length of the hand-over
@@ -411,7 +442,13 @@ __global__ __launch_bounds__(NT) void k_tile_batch2(BatchArgs a) {
     {
       real ld[G1::K][kPlanes];
       tile_loads<TW + 4, TH + 4>(d, a.src_buf + off, x0 - 2, y0 - 2, S1, ld);
+      if (a.cx && a.cconserve && threadIdx.x < kCorrVals)
+        ctot[threadIdx.x] = corr_total(a.cparts, dm, threadIdx.x);
       if (barrier_skip<true>(frozen)) continue;
+      if (a.cx)
+        tile_correct<TW + 4, TH + 4>(d, a, dm,
+                                     corr_shift(ctot, (long long)d.nx * d.ny, a.cconserve),
+                                     x0 - 2, y0 - 2, S1, ld);
       TileNode own[G1::K];
       tile_a<TW + 4, TH + 4>(d, S1, ld, own, L.l1, bad);
       __syncthreads();
