@@ -106,13 +106,18 @@ __device__ __forceinline__ EqCoef eq_coef(real r, real u, real v, real th) {
 }
 
 // The correction of one node: x, dl point at the node's domain in the
-// moments and increments (channel stride sc), i is its dense index; F and
-// sv hold its stored state and receive the corrected one.  Shared by
+// moments and increments (channel stride sc), i is its dense index.  Its
+// populations move by df, its entropy sv to corr_s(sv, q).  Shared by
 // k_corr_apply and the tile kernels, which apply a pending correction to
 // the state they load (identical arithmetic, so identical results).
-__device__ __forceinline__ void corr_node(const DomainArgs &d, const float *x, const float *dl,
-                                          long long sc, long long i, const CorrShift &c,
-                                          real (&F)[kQ], real &sv) {
+struct CorrDelta {
+  real df[kQ];
+  real cv, ls;  // the entropy moves by cv ls
+};
+
+__device__ __forceinline__ CorrDelta corr_delta(const DomainArgs &d, const float *x,
+                                                const float *dl, long long sc, long long i,
+                                                const CorrShift &c) {
   const real r = x[i], u = x[sc + i];
   const real v = x[2 * sc + i], th = x[3 * sc + i];
   const real dr = dl[i], du = dl[sc + i];
@@ -122,15 +127,18 @@ __device__ __forceinline__ void corr_node(const DomainArgs &d, const float *x, c
   const real u2 = (u + du) - c.bx * inv_r2, v2 = (v + dv) - c.by * inv_r2;
   const real th2 = th + dth;
   const EqCoef e1 = eq_coef(r, u, v, th), e2 = eq_coef(r2, u2, v2, th2);
-  real df[kQ];
+  CorrDelta q;
   const real dxxyy = (d.flags & kFlagFeq3) ? real(0) : e2.Axxyy - e1.Axxyy;
   project(e2.A0 - e1.A0, e2.Ax - e1.Ax, e2.Ay - e1.Ay, e2.Axx - e1.Axx, e2.Axy - e1.Axy,
-          e2.Ayy - e1.Ayy, e2.Axxy - e1.Axxy, e2.Axyy - e1.Axyy, dxxyy, df);
-#pragma unroll
-  for (int q = 0; q < kQ; ++q) F[q] += df[q];
-  const real cv = real(1) / d.inv_cv;
-  sv += cv * (log_r(th2 / th) - d.gm1 * log_r(r2 / r));
+          e2.Ayy - e1.Ayy, e2.Axxy - e1.Axxy, e2.Axyy - e1.Axyy, dxxyy, q.df);
+  q.cv = real(1) / d.inv_cv;
+  q.ls = log_r(th2 / th) - d.gm1 * log_r(r2 / r);
+  return q;
 }
+
+// The corrected entropy, one expression wherever it is formed (so any
+// fused multiply-add is placed alike).
+__device__ __forceinline__ real corr_s(real sv, const CorrDelta &q) { return sv + q.cv * q.ls; }
 
 __global__ __launch_bounds__(kCorrThreads) void k_corr_apply(CorrArgs a) {
   __shared__ double tot[kCorrVals];
@@ -144,15 +152,11 @@ __global__ __launch_bounds__(kCorrThreads) void k_corr_apply(CorrArgs a) {
   const long long base = (long long)k * a.n;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < a.n;
        i += (long long)gridDim.x * blockDim.x) {
+    const CorrDelta q = corr_delta(d, a.x + base, a.dl + base, a.sc, i, c);
     const long long o = state_off(d, i);
-    real F[kQ];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) F[q] = st[q * P + o];
-    real sv = st[9 * P + o];
-    corr_node(d, a.x + base, a.dl + base, a.sc, i, c, F, sv);
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) st[q * P + o] = F[q];
-    st[9 * P + o] = sv;
+    for (int p = 0; p < kQ; ++p) st[p * P + o] += q.df[p];
+    st[9 * P + o] = corr_s(st[9 * P + o], q);
   }
 }
 

@@ -326,8 +326,12 @@ hipError_t step_tile_batch2(const void *doms, const long long *offs, const void 
   a.rows = th;
 #define HLBM_TILE_CASE(W, H)                                                              \
   if (tw == W && th == H) {                                                               \
-    hipLaunchKernelGGL((k_tile_batch2<W, H, kTile2Threads>), dim3(grid), dim3(kTile2Threads), \
-                       0, st, a);                                                         \
+    if (a.cx)                                                                             \
+      hipLaunchKernelGGL((k_tile_batch2<W, H, kTile2Threads, true>), dim3(grid),          \
+                         dim3(kTile2Threads), 0, st, a);                                  \
+    else                                                                                  \
+      hipLaunchKernelGGL((k_tile_batch2<W, H, kTile2Threads, false>), dim3(grid),         \
+                         dim3(kTile2Threads), 0, st, a);                                  \
     return hipGetLastError();                                                             \
   }
   HLBM_TILE2_SHAPES(HLBM_TILE_CASE)
@@ -340,8 +344,8 @@ int tile2_blocks_per_cu(int tw, int th) {
   hipError_t e = hipErrorInvalidValue;
 #define HLBM_TILE_OCC(W, H)                                                                  \
   if (tw == W && th == H)                                                                    \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_batch2<W, H, kTile2Threads>, \
-                                                     kTile2Threads, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_batch2<W, H, kTile2Threads,  \
+                                                     false>, kTile2Threads, 0);
   HLBM_TILE2_SHAPES(HLBM_TILE_OCC)
 #undef HLBM_TILE_OCC
   return e == hipSuccess && n > 0 ? n : 1;
@@ -377,7 +381,10 @@ hipError_t step_tile_batch(const void *doms, const long long *offs, const void *
   a.rows = th;
 #define HLBM_TILE_CASE(W, H, NT)                                                         \
   if (tw == W && th == H) {                                                              \
-    hipLaunchKernelGGL((k_tile_batch<W, H, NT>), dim3(grid), dim3(NT), 0, st, a);       \
+    if (a.cx)                                                                            \
+      hipLaunchKernelGGL((k_tile_batch<W, H, NT, true>), dim3(grid), dim3(NT), 0, st, a); \
+    else                                                                                 \
+      hipLaunchKernelGGL((k_tile_batch<W, H, NT, false>), dim3(grid), dim3(NT), 0, st, a); \
     return hipGetLastError();                                                            \
   }
   HLBM_TILE_SHAPES(HLBM_TILE_CASE)
@@ -390,7 +397,7 @@ int tile_blocks_per_cu(int tw, int th) {
   hipError_t e = hipErrorInvalidValue;
 #define HLBM_TILE_OCC(W, H, NT)                                                             \
   if (tw == W && th == H)                                                                   \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_batch<W, H, NT>, NT, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_tile_batch<W, H, NT, false>, NT, 0);
   HLBM_TILE_SHAPES(HLBM_TILE_OCC)
 #undef HLBM_TILE_OCC
   return e == hipSuccess && n > 0 ? n : 1;

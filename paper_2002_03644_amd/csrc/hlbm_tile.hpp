@@ -156,14 +156,11 @@ __device__ __forceinline__ void tile_correct(const DomainArgs &d, const BatchArg
     if (!S.live[k]) continue;
     const int cx = map_index(x0 + S.px[k], d.nx, d.bcx);
     const int cy = map_index(y0 + S.py[k], d.ny, d.bcy);
-    real F[kQ];
+    const CorrDelta q = corr_delta(d, a.cx + fo, a.cdl + fo, a.mom_sc,
+                                   (long long)cy * d.nx + cx, c);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) F[q] = ld[k][q];
-    real sv = ld[k][9];
-    corr_node(d, a.cx + fo, a.cdl + fo, a.mom_sc, (long long)cy * d.nx + cx, c, F, sv);
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) ld[k][q] = F[q];
-    ld[k][9] = sv;
+    for (int p = 0; p < kQ; ++p) ld[k][p] += q.df[p];
+    ld[k][9] = corr_s(ld[k][9], q);
   }
 }
 
@@ -367,7 +364,9 @@ __device__ __forceinline__ void tile_c_store(const DomainArgs &d, real *dst0, co
 
 // Persistent walk over (domain, tile x, tile y) items with the strip
 // kernels' per-workgroup skip of frozen domains: one step per launch.
-template <int TW, int TH, int NT>
+// kCorr: the variant that applies a pending correction (a.cx set), built
+// apart so the plain steps do not carry its registers.
+template <int TW, int TH, int NT, bool kCorr>
 __global__ __launch_bounds__(NT) void k_tile_batch(BatchArgs a) {
   __shared__ TileLDS<TW, TH> L;
   __shared__ double ctot[kCorrVals];  // a pending correction's totals
@@ -384,12 +383,12 @@ __global__ __launch_bounds__(NT) void k_tile_batch(BatchArgs a) {
     const int y0 = __builtin_amdgcn_readfirstlane(w.z) * TH;
     real ld[G::K][kPlanes];
     tile_loads<TW, TH>(d, a.src_buf + off, x0, y0, S, ld);
-    if (a.cx && a.cconserve && threadIdx.x < kCorrVals)
+    if (kCorr && a.cconserve && threadIdx.x < kCorrVals)
       ctot[threadIdx.x] = corr_total(a.cparts, dm, threadIdx.x);
     // one skip decision per workgroup; the barrier also keeps the previous
     // item's LDS reads ahead of this item's writes, and publishes ctot
     if (barrier_skip<true>(frozen)) continue;
-    if (a.cx)
+    if constexpr (kCorr)
       tile_correct<TW, TH>(d, a, dm, corr_shift(ctot, (long long)d.nx * d.ny, a.cconserve), x0,
                            y0, S, ld);
     TileNode own[G::K];
@@ -419,8 +418,11 @@ union TileLDS2 {
 // virtual tile (TW + 4) x (TH + 4) at (x0 - 2, y0 - 2), whose results are
 // exactly the intermediate state on the second step's tile and radius-2
 // halo; step two on the TW x TH tile.
-template <int TW, int TH, int NT>
-__global__ __launch_bounds__(NT) void k_tile_batch2(BatchArgs a) {
+// Register budget: two workgroups of NT threads per compute unit (the
+// correction variant would otherwise take more registers than that allows).
+template <int TW, int TH, int NT, bool kCorr>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2 * NT / 256)))
+void k_tile_batch2(BatchArgs a) {
   __shared__ TileLDS2<TW, TH> L;
   __shared__ double ctot[kCorrVals];  // a pending correction's totals
   using G1 = TileGeom<TW + 4, TH + 4, NT>;
@@ -442,10 +444,10 @@ __global__ __launch_bounds__(NT) void k_tile_batch2(BatchArgs a) {
     {
       real ld[G1::K][kPlanes];
       tile_loads<TW + 4, TH + 4>(d, a.src_buf + off, x0 - 2, y0 - 2, S1, ld);
-      if (a.cx && a.cconserve && threadIdx.x < kCorrVals)
+      if (kCorr && a.cconserve && threadIdx.x < kCorrVals)
         ctot[threadIdx.x] = corr_total(a.cparts, dm, threadIdx.x);
       if (barrier_skip<true>(frozen)) continue;
-      if (a.cx)
+      if constexpr (kCorr)
         tile_correct<TW + 4, TH + 4>(d, a, dm,
                                      corr_shift(ctot, (long long)d.nx * d.ny, a.cconserve),
                                      x0 - 2, y0 - 2, S1, ld);
