@@ -305,15 +305,16 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
 // row y0+j-7, with one barrier per step.  Layers 2 and 3 read only the
 // newest row of their input ring (three fragments per strip) and add its
 // three tap rows to the three output rows it touches, whose accumulators
-// rotate; each row still sums its taps in the order t = 0..8.  Each wave has
-// one role, which balances the matrix-core work (about
-// 36 MFMAs per wave and step) and keeps only that role's weights in
-// registers:
-//   wave 0: layer 2, strips 0 and 1      wave 2: layer 2, strip 4, and layer 1
-//   wave 1: layer 2, strips 2 and 3      wave 3: output layer, four strips
+// rotate; each row still sums its taps in the order t = 0..8.  Each of the
+// eight waves has one role, which balances the matrix-core work (18-20
+// MFMAs per wave and step: half of what four waves had, so each barrier
+// step's serial chain is half as long) and keeps only that role's weights
+// in registers:
+//   waves 0-4: layer 2, strip = wave      wave 5: layer 1, five strips
+//   waves 6-7: output layer, two of its four strips each
 // The arithmetic (tap order, FP32 accumulation, BF16 rounding points) is that
 // of k_prep and k_conv, so both paths give identical results.
-constexpr int kFuseCols = 80, kFuseOut = 64, kFuseWaves = 4, kRing = 4;
+constexpr int kFuseCols = 80, kFuseOut = 64, kFuseWaves = 8, kRing = 4;
 constexpr int kFuseMaxRows = 32;
 // LDS pixel stride of the layer rings in BF16 elements: 32 channels padded to
 // 40 (80 bytes), which spreads the 16-byte reads of a fragment's 16 pixels
@@ -331,7 +332,9 @@ struct FusedArgs {
   float mean[4], inv_std[4], os[4], om[4], clip;
 };
 
-__global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
+// two workgroups per compute unit (LDS allows two): 128 registers per lane
+__global__ __launch_bounds__(64 * kFuseWaves) __attribute__((amdgpu_waves_per_eu(4)))
+void k_cnn_fused(FusedArgs a) {
   __shared__ __attribute__((aligned(16))) bf16 in_tile[kFuseMaxRows + 6][kFuseCols][4];
   __shared__ __attribute__((aligned(16))) bf16 l1_ring[kRing][kFuseCols][kPixPad];
   __shared__ __attribute__((aligned(16))) bf16 l2_ring[kRing][kFuseCols][kPixPad];
@@ -375,9 +378,9 @@ __global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
     *(bf16x4 *)dst = o;
   };
 
-  if (wave < 3) {
-    // ---- layer 2 on strips s0 .. s0 + ns - 1 (and layer 1 for wave 2)
-    const int s0 = 2 * wave, ns = wave < 2 ? 2 : 1;
+  if (wave < 5) {
+    // ---- layer 2 on strip `wave`
+    const int col = 16 * wave + n;
     bf16x8 w2[9][2];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
@@ -388,23 +391,58 @@ __global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
     for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) bias2[nb][r] = a.b2[16 * nb + 4 * g + r];
-    bf16x8 w1[2][2];
-    f32x4 bias1[2];
-    if (wave == 2) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) w1[h][nb] = a.wp[kPk1 + (h * 2 + nb) * 64 + lane];
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) bias1[nb][r] = a.b1[16 * nb + 4 * g + r];
-    }
-    // layer-2 rows in progress per strip: a2m one tap row short, a2o two
-    f32x4 a2m[2][2] = {}, a2o[2][2] = {};
+    // layer-2 rows in progress: a2m one tap row short, a2o two
+    f32x4 a2m[2] = {}, a2o[2] = {};
     for (int j = 1; j <= R + 6; ++j) {
       __syncthreads();
-      if (wave == 2 && j <= R + 4) {     // layer 1, row y0 + j - 3: tile rows j-1+dy
+      if (j >= 2 && j <= R + 5) {
+        // the newest layer-1 row y0 + j - 4 (written at step j - 1) is read
+        // once and gives its tap row dy = 0 to layer-2 row y0 + j - 3
+        // (started from the bias), dy = 1 to row y0 + j - 4 and dy = 2 to
+        // row y0 + j - 5, which is then complete.  Each row still
+        // accumulates its taps in the order t = 0 .. 8.
+        const int slot = (j - 1) & 3;
+        bf16x8 bv[3];
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+          bv[dx] = *(const bf16x8 *)&l1_ring[slot][clampc(col + dx - 1)][8 * g];
+        __builtin_amdgcn_sched_barrier(0);
+        f32x4 an[2] = {bias2[0], bias2[1]};
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) {
+            an[nb] = mfma(w2[dx][nb], bv[dx], an[nb]);
+            a2m[nb] = mfma(w2[3 + dx][nb], bv[dx], a2m[nb]);
+            a2o[nb] = mfma(w2[6 + dx][nb], bv[dx], a2o[nb]);
+          }
+        if (j >= 4) {
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+            relu_store(&l2_ring[j & 3][col][16 * nb + 4 * g], a2o[nb]);
+        }
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          a2o[nb] = a2m[nb];
+          a2m[nb] = an[nb];
+        }
+      }
+    }
+  } else if (wave == 5) {
+    // ---- layer 1 on the five strips
+    bf16x8 w1[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) w1[h][nb] = a.wp[kPk1 + (h * 2 + nb) * 64 + lane];
+    f32x4 bias1[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bias1[nb][r] = a.b1[16 * nb + 4 * g + r];
+    for (int j = 1; j <= R + 6; ++j) {
+      __syncthreads();
+      if (j <= R + 4) {     // layer-1 row y0 + j - 3: tile rows j-1+dy
         for (int st = 0; st < 5; ++st) {
           const int col = 16 * st + n;
           bf16x4 v[2][2];
@@ -430,47 +468,10 @@ __global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
           for (int nb = 0; nb < 2; ++nb) relu_store(&l1_ring[j & 3][col][16 * nb + 4 * g], acc[nb]);
         }
       }
-      if (j >= 2 && j <= R + 5) {
-        // layer 2: the newest layer-1 row y0 + j - 4 (written at step j - 1)
-        // is read once and gives its tap row dy = 0 to layer-2 row y0 + j - 3
-        // (started from the bias), dy = 1 to row y0 + j - 4 and dy = 2 to row
-        // y0 + j - 5, which is then complete.  Each row still accumulates its
-        // taps in the order t = 0 .. 8.
-        const int slot = (j - 1) & 3;
-#pragma unroll
-        for (int si = 0; si < 2; ++si) {
-          if (si < ns) {
-            const int col = 16 * (s0 + si) + n;
-            bf16x8 bv[3];
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx)
-              bv[dx] = *(const bf16x8 *)&l1_ring[slot][clampc(col + dx - 1)][8 * g];
-            __builtin_amdgcn_sched_barrier(0);
-            f32x4 an[2] = {bias2[0], bias2[1]};
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx)
-#pragma unroll
-              for (int nb = 0; nb < 2; ++nb) {
-                an[nb] = mfma(w2[dx][nb], bv[dx], an[nb]);
-                a2m[si][nb] = mfma(w2[3 + dx][nb], bv[dx], a2m[si][nb]);
-                a2o[si][nb] = mfma(w2[6 + dx][nb], bv[dx], a2o[si][nb]);
-              }
-            if (j >= 4) {
-#pragma unroll
-              for (int nb = 0; nb < 2; ++nb)
-                relu_store(&l2_ring[j & 3][col][16 * nb + 4 * g], a2o[si][nb]);
-            }
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-              a2o[si][nb] = a2m[si][nb];
-              a2m[si][nb] = an[nb];
-            }
-          }
-        }
-      }
     }
   } else {
-    // ---- output layer on the four strips covering columns 8 .. 71
+    // ---- output layer on two of the four strips covering columns 8 .. 71
+    const int s0 = 2 * (wave - 6);
     bf16x8 w3[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) w3[t] = a.wp[kPk3 + t * 64 + lane];
@@ -478,7 +479,7 @@ __global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) bias3[r] = (4 * g + r < kOut) ? a.b3[4 * g + r] : 0.f;
     // output rows in progress per strip: a3m one tap row short, a3o two
-    f32x4 a3m[4] = {}, a3o[4] = {};
+    f32x4 a3m[2] = {}, a3o[2] = {};
     for (int j = 1; j <= R + 6; ++j) {
       __syncthreads();
       if (j < 5) continue;
@@ -488,8 +489,8 @@ __global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
       const int slot = (j - 1) & 3;
       const long long row = (long long)(y0 + j - 7) * W;
 #pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int col = 8 + 16 * st + n;
+      for (int si = 0; si < 2; ++si) {
+        const int col = 8 + 16 * (s0 + si) + n;
         bf16x8 bv[3];
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx)
@@ -499,12 +500,12 @@ __global__ __launch_bounds__(64 * kFuseWaves) void k_cnn_fused(FusedArgs a) {
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
           an = mfma(w3[dx], bv[dx], an);
-          a3m[st] = mfma(w3[3 + dx], bv[dx], a3m[st]);
-          a3o[st] = mfma(w3[6 + dx], bv[dx], a3o[st]);
+          a3m[si] = mfma(w3[3 + dx], bv[dx], a3m[si]);
+          a3o[si] = mfma(w3[6 + dx], bv[dx], a3o[si]);
         }
-        const f32x4 acc = a3o[st];
-        a3o[st] = a3m[st];
-        a3m[st] = an;
+        const f32x4 acc = a3o[si];
+        a3o[si] = a3m[si];
+        a3m[si] = an;
         if (j >= 7 && g == 0) {
           const long long i = row + x0 + col - 8;
 #pragma unroll
