@@ -379,3 +379,36 @@ def test_closure_step_tiles_mixed_call_lengths():
         torch.cuda.synchronize()
         assert torch.equal(moments_cat(A), moments_cat(E)), rep
     assert A.steps == E.steps == 4 * 12
+
+
+def test_closure_step_one_step_tiles_equal_manual_sequence():
+    """Domains extrapolated along x take one step per launch: the one-step
+    tile kernel then applies the pending correction in the cycle's first
+    launch (three launches per cycle); the result equals a manual
+    step/moments/forward/correct sequence bit for bit."""
+    import dataclasses
+    params, flds = closure_batch(count=3, n=64, seed=50)
+    params = [dataclasses.replace(p, bc_x="extrapolate") for p in params]
+    net_params = rand_params(51)
+    net_params[2] = (net_params[2][0] * 0.01, net_params[2][1] * 0.0)
+    A = BatchSolver(params, flds)
+    M = BatchSolver(params, flds)
+    for S in (A, M):
+        S.set_tile(32, 16, kernel="tiles")
+    assert A.plan() == (1, "tiles", 32, 16)
+    na, nm = (make_net(3, 64, 64, net_params) for _ in range(2))
+    for nt in (na, nm):
+        nt.set_norm(np.array([1.0, 0, 0, 0.2], np.float32), np.array([0.03, 0.05, 0.05, 0.01], np.float32),
+                    np.zeros(4, np.float32), np.array([1e-4, 1e-4, 1e-4, 1e-5], np.float32))
+    x = torch.empty(4, 3, 64 * 64, device="cuda")
+    for rep in range(2):
+        A.closure_step(na, 3, every=3, graph=True)
+        for _ in range(3):
+            M.step(3, graph=False)
+            x.copy_(moments_cat(M))
+            dl = nm.forward(x, batch=3, sstride=64 * 64, cstride=3 * 64 * 64)
+            d = dl.permute(1, 0, 2, 3).reshape(4, 3, -1).contiguous()
+            M.correct(x, d, conserve=True)
+        torch.cuda.synchronize()
+        assert torch.equal(moments_cat(A), moments_cat(M)), rep
+    assert A.steps == M.steps == 18
