@@ -348,26 +348,41 @@ void k_cnn_fused(FusedArgs a) {
   const int x0 = cb * kFuseOut, y0 = rb * R;
 
   // stage the standardised input: tile row q holds image row y0 - 3 + q.
-  // All rows' loads are issued before the first conversion, so the staging
-  // costs one memory latency rather than one per row.
-  for (int p = tid; p < kFuseCols * 4; p += 64 * kFuseWaves) {
-    const int lc = p % kFuseCols, lch = p / kFuseCols;
-    int gx = x0 - 8 + lc;
-    gx = gx < 0 ? gx + W : (gx >= W ? gx - W : gx);
-    const float *src = a.x + b * a.sb + lch * a.sc + gx;
-    float v[kFuseMaxRows + 6];
+  // Thread t converts the pixels t, t + 512, ... of the (rows + 6) x 80
+  // region (a wave covers consecutive columns, so each channel's loads are
+  // coalesced); the four channels' loads of all its pixels are issued before
+  // the first conversion, so the staging costs one memory latency, and each
+  // pixel is one 8-byte LDS write.
+  {
+    constexpr int kT = 64 * kFuseWaves;
+    constexpr int kIt = ((kFuseMaxRows + 6) * kFuseCols + kT - 1) / kT;
+    const int npix = (R + 6) * kFuseCols;
+    float v[kIt][4];
 #pragma unroll
-    for (int q = 0; q < kFuseMaxRows + 6; ++q) {
-      if (q < R + 6) {
+    for (int it = 0; it < kIt; ++it) {
+      const int p = tid + it * kT;
+      if (p < npix) {
+        const int q = p / kFuseCols, lc = p - q * kFuseCols;
+        int gx = x0 - 8 + lc;
+        gx = gx < 0 ? gx + W : (gx >= W ? gx - W : gx);
         int yy = y0 - 3 + q;   // in [-3, H + 2]: one wrap suffices (H >= 4)
         yy = yy < 0 ? yy + H : (yy >= H ? yy - H : yy);
-        v[q] = src[(long long)yy * W];
+        const float *src = a.x + b * a.sb + (long long)yy * W + gx;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) v[it][ch] = src[ch * a.sc];
       }
     }
-    const float mean = a.mean[lch], inv = a.inv_std[lch];
 #pragma unroll
-    for (int q = 0; q < kFuseMaxRows + 6; ++q)
-      if (q < R + 6) in_tile[q][lc][lch] = (bf16)((v[q] - mean) * inv);
+    for (int it = 0; it < kIt; ++it) {
+      const int p = tid + it * kT;
+      if (p < npix) {
+        const int q = p / kFuseCols, lc = p - q * kFuseCols;
+        bf16x4 o;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) o[ch] = (bf16)((v[it][ch] - a.mean[ch]) * a.inv_std[ch]);
+        *(bf16x4 *)&in_tile[q][lc][0] = o;
+      }
+    }
   }
   // a neighbour outside the region reads the edge column instead
   auto clampc = [](int c) { return c < 0 ? 0 : (c >= kFuseCols ? kFuseCols - 1 : c); };
