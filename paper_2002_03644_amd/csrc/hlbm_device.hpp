@@ -614,12 +614,32 @@ struct BatchArgs {
   const float *cx, *cdl;
   const double *cparts;
   int cconserve;
+  int xcd_walk;  // 1: each XCD walks a contiguous range of the items (see tile_walk)
 };
+
+// This workgroup's share of the persistent walk over n items: items first,
+// first + step, ... below end.  Workgroups are dealt round-robin to the
+// eight XCDs (workgroup b to XCD b mod 8).  With xcd set (and at least eight
+// workgroups) the walk gives XCD x the contiguous item range
+// [x n / 8, (x + 1) n / 8), taken in order by its workgroups, so tiles and
+// strips that share halo rows and columns are loaded through one L2;
+// otherwise workgroup b takes every gridDim.x-th item from b.
+struct TileWalk {
+  int first, step, end;
+};
+__device__ __forceinline__ TileWalk tile_walk(const int n, const int xcd) {
+  const int g = (int)gridDim.x, b = (int)blockIdx.x;
+  if (!xcd || g < 8) return TileWalk{b, g, n};
+  const int x = b & 7;
+  const int lo = (int)((long long)x * n / 8), hi = (int)((long long)(x + 1) * n / 8);
+  return TileWalk{lo + (b >> 3), (g - x + 7) >> 3, hi};
+}
 
 template <int CW>
 __global__ __launch_bounds__(CW + 64) void k_step_batch(BatchArgs a) {
   __shared__ TileRings<CW> R;
-  for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+  const TileWalk walk = tile_walk(a.nitems, a.xcd_walk);
+  for (int it = walk.first; it < walk.end; it += walk.step) {
     const int4 w = a.items[it];
     const int dm = __builtin_amdgcn_readfirstlane(w.x);
     const DomainArgs d = a.doms[dm];

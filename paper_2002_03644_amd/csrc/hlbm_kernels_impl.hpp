@@ -190,8 +190,9 @@ void pack_domains(const HostDomain *h, int count, void *host_out) {
 
 hipError_t step_batch(const void *doms, const long long *offs, const void *items, int nitems,
                       const void *src, void *dst, unsigned *status, int rows, int cw, int grid,
-                      hipStream_t st) {
+                      int xcd_walk, hipStream_t st) {
   BatchArgs a;
+  a.xcd_walk = xcd_walk;
   a.doms = (const DomainArgs *)doms;
   a.offs = offs;
   a.items = (const int4 *)items;
@@ -227,8 +228,9 @@ hipError_t step_batch(const void *doms, const long long *offs, const void *items
 
 hipError_t step_batch2(const void *doms, const long long *offs, const void *items, int nitems,
                        const void *src, void *dst, unsigned *status, int rows, int cw, int grid,
-                       hipStream_t st) {
+                       int xcd_walk, hipStream_t st) {
   BatchArgs a;
+  a.xcd_walk = xcd_walk;
   a.doms = (const DomainArgs *)doms;
   a.offs = offs;
   a.items = (const int4 *)items;
@@ -306,9 +308,10 @@ bool tile2_shape_supported(int tw, int th) {
 
 hipError_t step_tile_batch2(const void *doms, const long long *offs, const void *items,
                             int nitems, const void *src, void *dst, unsigned *status, int tw,
-                            int th, int grid, void *mom, const long long *foffs,
+                            int th, int grid, int xcd_walk, void *mom, const long long *foffs,
                             long long mom_sc, const TileCorr &corr, hipStream_t st) {
   BatchArgs a;
+  a.xcd_walk = xcd_walk;
   a.mom = (real *)mom;
   a.foffs = foffs;
   a.mom_sc = mom_sc;
@@ -361,9 +364,10 @@ bool tile_shape_supported(int tw, int th) {
 
 hipError_t step_tile_batch(const void *doms, const long long *offs, const void *items,
                            int nitems, const void *src, void *dst, unsigned *status, int tw,
-                           int th, int grid, void *mom, const long long *foffs,
+                           int th, int grid, int xcd_walk, void *mom, const long long *foffs,
                            long long mom_sc, const TileCorr &corr, hipStream_t st) {
   BatchArgs a;
+  a.xcd_walk = xcd_walk;
   a.mom = (real *)mom;
   a.foffs = foffs;
   a.mom_sc = mom_sc;

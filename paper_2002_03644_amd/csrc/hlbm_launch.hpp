@@ -134,21 +134,23 @@ struct TileCorr {
   void pack_domains(const HostDomain *h, int count, void *host_out);                        \
   hipError_t step_batch(const void *doms, const long long *offs, const void *items,          \
                         int nitems, const void *src, void *dst, unsigned *status, int rows, \
-                        int cw, int grid, hipStream_t st);                                  \
+                        int cw, int grid, int xcd_walk, hipStream_t st);                    \
   int batch_blocks_per_cu(int cw);                                                          \
   hipError_t step_batch2(const void *doms, const long long *offs, const void *items,         \
                          int nitems, const void *src, void *dst, unsigned *status, int rows,\
-                         int cw, int grid, hipStream_t st);                                 \
+                         int cw, int grid, int xcd_walk, hipStream_t st);                   \
   int batch2_blocks_per_cu(int cw);                                                         \
   hipError_t step_tile_batch(const void *doms, const long long *offs, const void *items,     \
                              int nitems, const void *src, void *dst, unsigned *status,       \
-                             int tw, int th, int grid, void *mom, const long long *foffs,    \
+                             int tw, int th, int grid, int xcd_walk, void *mom,              \
+                             const long long *foffs,                                         \
                              long long mom_sc, const TileCorr &corr, hipStream_t st);        \
   int tile_blocks_per_cu(int tw, int th);                                                   \
   bool tile_shape_supported(int tw, int th);                                                \
   hipError_t step_tile_batch2(const void *doms, const long long *offs, const void *items,    \
                               int nitems, const void *src, void *dst, unsigned *status,      \
-                              int tw, int th, int grid, void *mom, const long long *foffs,   \
+                              int tw, int th, int grid, int xcd_walk, void *mom,             \
+                              const long long *foffs,                                        \
                               long long mom_sc, const TileCorr &corr, hipStream_t st);       \
   int tile2_blocks_per_cu(int tw, int th);                                                  \
   bool tile2_shape_supported(int tw, int th);                                               \

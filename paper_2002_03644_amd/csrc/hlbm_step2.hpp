@@ -353,7 +353,8 @@ __global__ __launch_bounds__(step2_threads(CW)) void k_step2(StepArgs a) {
 template <int CW>
 __global__ __launch_bounds__(step2_threads(CW)) void k_step_batch2(BatchArgs a) {
   __shared__ TileRings2<CW> R;
-  for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+  const TileWalk walk = tile_walk(a.nitems, a.xcd_walk);
+  for (int it = walk.first; it < walk.end; it += walk.step) {
     const int4 w = a.items[it];
     const int dm = __builtin_amdgcn_readfirstlane(w.x);
     const DomainArgs d = a.doms[dm];

@@ -372,7 +372,8 @@ __global__ __launch_bounds__(NT) void k_tile_batch(BatchArgs a) {
   __shared__ double ctot[kCorrVals];  // a pending correction's totals
   using G = TileGeom<TW, TH, NT>;
   const TileSlots<TW, TH, NT> S = tile_slots<TW, TH, NT>(threadIdx.x);
-  for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+  const TileWalk walk = tile_walk(a.nitems, a.xcd_walk);
+  for (int it = walk.first; it < walk.end; it += walk.step) {
     const int4 w = a.items[it];
     const int dm = __builtin_amdgcn_readfirstlane(w.x);
     const DomainArgs d = a.doms[dm];
@@ -430,7 +431,8 @@ void k_tile_batch2(BatchArgs a) {
   constexpr int VW = TW + 4;  // row length of the hand-over
   const TileSlots<TW + 4, TH + 4, NT> S1 = tile_slots<TW + 4, TH + 4, NT>(threadIdx.x);
   const TileSlots<TW, TH, NT> S2 = tile_slots<TW, TH, NT>(threadIdx.x);
-  for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+  const TileWalk walk = tile_walk(a.nitems, a.xcd_walk);
+  for (int it = walk.first; it < walk.end; it += walk.step) {
     const int4 w = a.items[it];
     const int dm = __builtin_amdgcn_readfirstlane(w.x);
     const DomainArgs d = a.doms[dm];
