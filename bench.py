@@ -181,7 +181,8 @@ def main():
     ap.add_argument("--every", type=int, default=1,
                     help="closure workload: plain steps per correction")
     ap.add_argument("--batch-kernel", default="strips", choices=["strips", "tiles"],
-                    help="batch workload with --tile-w/--tile-h: the kernel those name")
+                    help="batch and closure workloads with --tile-w/--tile-h: the kernel "
+                         "those name")
     ap.add_argument("--steps-per-launch", type=int, default=0, choices=[0, 1, 2],
                     help="0: the library's plan (two steps per launch here), 1 or 2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -404,7 +405,11 @@ def bench_closure(args):
         fields.append(tuple(np.ascontiguousarray(a[::f, ::f]) for a in (r, u, v, t)))
         params.append(L._params(nc, setup.mu_coarse, float(t[0, 0]), setup))
     B = BatchSolver(params, fields)
-    bk, tw, th = B.autotune(steps=10)
+    if args.tile_w and args.tile_h:  # a given shape (profiling runs), else the autotuner's
+        B.set_tile(args.tile_w, args.tile_h, kernel=args.batch_kernel)
+        bk, tw, th = args.batch_kernel, args.tile_w, args.tile_h
+    else:
+        bk, tw, th = B.autotune(steps=10)
     net = CNN(len(seeds), nc, nc, L.initial_params(0))
     net.set_norm(np.array([1, 0, 0, 0.2], np.float32), np.array([0.1, 0.1, 0.1, 0.01], np.float32),
                  np.zeros(4, np.float32), np.array([1e-3, 1e-3, 1e-3, 1e-4], np.float32))
