@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -41,11 +42,22 @@ TRAFFIC_FILES = {1: os.path.join(ROOT, "profiles", "k_step_f32_turbulence8192_tr
 KERNEL_NAMES = {1: "hlbm::f32::k_step<{w}>", 2: "hlbm::f32::k_step2<{w}>"}
 
 
+def code_text(src: str) -> str:
+    """C++ source without comments, string-free by construction here, with
+    runs of whitespace collapsed: the part of a file that the compiler sees
+    as code, so that editing a comment leaves the hash alone."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def kernel_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the step kernels' code (see
+    code_text), the key the committed counter summaries are checked by."""
     h = hashlib.sha256()
     for path in KERNEL_SRCS:
-        with open(path, "rb") as fh:
-            h.update(fh.read())
+        with open(path, encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -526,7 +526,7 @@ constexpr size_t kXcdWalkBytes = (size_t)256 << 20;
 constexpr int kTileShapes[5][2] = {{32, 8}, {32, 16}, {64, 8}, {32, 32}, {64, 16}};
 
 int batch_items_for(const hlbm_batch *b, int tw, int th, std::vector<int> *out) {
-  // largest domains first: the round-robin walk then ends on small items
+  // largest domains first: every workgroup's walk then ends on small items
   std::vector<int> order(b->count);
   for (int k = 0; k < b->count; ++k) order[k] = k;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {

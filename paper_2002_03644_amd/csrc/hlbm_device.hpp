@@ -588,14 +588,14 @@ __global__ __launch_bounds__(CW + 64) void k_step(StepArgs a) {
   sweep_tile<CW>(a.d, a.src, a.dst, a.status, a.rows, bid % a.nbx, bid / a.nbx, 0, R);
 }
 
-// Batched step: a persistent grid walks a list of (domain, tile) items,
-// statically round-robin (no atomics: the launch can be captured and
+// Batched step: a persistent grid walks a list of (domain, tile) items in a
+// static order (tile_walk; no atomics: the launch can be captured and
 // replayed).  Items of a domain whose divergence flag is set are skipped, so
 // a diverged domain freezes while the others go on (see domain_frozen).
 struct BatchArgs {
   const DomainArgs *doms;
   const long long *offs;  // element offset of each domain's state in a buffer
-  const int4 *items;      // (domain, bx, by, unused)
+  const int4 *items;      // (domain, bx, by, strip rows; the kernels read the first three)
   int nitems;
   const real *src_buf;
   real *dst_buf;
