@@ -504,10 +504,18 @@ struct hlbm_batch {
   // pairs (fewer replays, so fewer gaps between them, for short steps)
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int graph_cur[2] = {-1, -1};
-  hipGraphExec_t cgraph = nullptr;    // captured corrected steps (hlbm_closure_step)
-  int cgraph_cur = -1, cgraph_conserve = -1, cgraph_version = -1, cgraph_every = -1;
-  int cgraph_pending = -1;  // whether the captured cycles start with a pending correction
-  const hlbm_cnn *cgraph_net = nullptr;
+  // captured corrected cycles (hlbm_closure_step): cgraph[0] two cycles,
+  // cgraph[1] kLongCycles, each with the key it was captured under
+  hipGraphExec_t cgraph[2] = {nullptr, nullptr};
+  struct ClosureKey {
+    int cur = -1, conserve = -1, version = -1, every = -1;
+    int pending = -1;  // whether the captured cycles start with a pending correction
+    const hlbm_cnn *net = nullptr;
+    bool operator==(const ClosureKey &o) const {
+      return cur == o.cur && conserve == o.conserve && version == o.version &&
+             every == o.every && pending == o.pending && net == o.net;
+    }
+  } cgraph_key[2];
   int xcd_walk = 0;  // batch kernels: each XCD walks a contiguous range of the items
 };
 
@@ -647,9 +655,9 @@ hipError_t batch_upload_items(hlbm_batch *b, int kind, int tw, int th, hipStream
     if (g) (void)hipGraphExecDestroy(g);
     g = nullptr;
   }
-  if (b->cgraph) {
-    (void)hipGraphExecDestroy(b->cgraph);
-    b->cgraph = nullptr;
+  for (hipGraphExec_t &g : b->cgraph) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
   }
   return hipSuccess;
 }
@@ -661,6 +669,8 @@ hipError_t batch_launch(hlbm_batch *b, int from, hipStream_t st);
 // 256^2: 23 us per step) costs about 8 %; sixteen steps per replay recover
 // it (21.2 us).
 constexpr int kLongPairs = 8;
+// Corrected cycles per long closure graph (see hlbm_closure_step).
+constexpr int kLongCycles = 8;
 
 // Graph `which` of `pairs` ping-pong pairs from the current buffer (an even
 // number of steps leaves the state there), captured on first use and again
@@ -1022,7 +1032,8 @@ void hlbm_batch_destroy(hlbm_batch *b) {
   if (!b) return;
   for (hipGraphExec_t g : b->graph)
     if (g) (void)hipGraphExecDestroy(g);
-  if (b->cgraph) (void)hipGraphExecDestroy(b->cgraph);
+  for (hipGraphExec_t g : b->cgraph)
+    if (g) (void)hipGraphExecDestroy(g);
   delete b;
 }
 
@@ -1147,44 +1158,50 @@ int hlbm_closure_step(hlbm_batch *b, hlbm_cnn *c, int32_t ncycles, int32_t every
     b->steps += every;
     --n;
   }
-  if (use_graph && n >= 2) {
-    // two cycles per graph: the state returns to the same buffer
-    if (!b->cgraph || b->cgraph_cur != b->cur || b->cgraph_net != c ||
-        b->cgraph_conserve != conserve || b->cgraph_version != hlbm_cnn_version(c) ||
-        b->cgraph_every != every || b->cgraph_pending != (int)pending) {
-      if (b->cgraph) {
-        (void)hipGraphExecDestroy(b->cgraph);
-        b->cgraph = nullptr;
+  // graphs of kLongCycles cycles while enough remain, then of two (an even
+  // count returns the state to the buffer it started from); the rest runs
+  // eagerly.  Fewer replays leave fewer gaps between them.
+  for (int which = 1; use_graph && which >= 0; --which) {
+    const int len = which ? kLongCycles : 2;
+    if (n < len) continue;
+    hlbm_batch::ClosureKey key;
+    key.cur = b->cur;
+    key.conserve = conserve;
+    key.version = hlbm_cnn_version(c);
+    key.every = every;
+    key.pending = (int)pending;
+    key.net = c;
+    hipGraphExec_t &gx = b->cgraph[which];
+    if (!gx || !(b->cgraph_key[which] == key)) {
+      if (gx) {
+        (void)hipGraphExecDestroy(gx);
+        gx = nullptr;
       }
       const int cur0 = b->cur;
       hipGraph_t g = nullptr;
       if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return HLBM_EHIP;
       bool gp = pending;
-      int rc1 = closure_once(b, c, every, conserve, st, gp);
-      int rc2 = rc1 == HLBM_OK ? closure_once(b, c, every, conserve, st, gp) : rc1;
+      int rc = HLBM_OK;
+      for (int k = 0; k < len && rc == HLBM_OK; ++k)
+        rc = closure_once(b, c, every, conserve, st, gp);
       hipError_t e = hipStreamEndCapture(st, &g);
       b->cur = cur0;   // capture only recorded the launches
-      if (rc1 != HLBM_OK || rc2 != HLBM_OK || e != hipSuccess) {
+      if (rc != HLBM_OK || e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         return HLBM_EHIP;
       }
-      e = hipGraphInstantiate(&b->cgraph, g, nullptr, nullptr, 0);
+      e = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if (e != hipSuccess) {
-        b->cgraph = nullptr;
+        gx = nullptr;
         return HLBM_EHIP;
       }
-      b->cgraph_cur = b->cur;
-      b->cgraph_net = c;
-      b->cgraph_conserve = conserve;
-      b->cgraph_version = hlbm_cnn_version(c);
-      b->cgraph_every = every;
-      b->cgraph_pending = (int)pending;
+      b->cgraph_key[which] = key;
     }
-    for (; n >= 2; n -= 2) {
-      if (hipGraphLaunch(b->cgraph, st) != hipSuccess) return HLBM_EHIP;
-      b->steps += 2 * every;
+    for (; n >= len; n -= len) {
+      if (hipGraphLaunch(gx, st) != hipSuccess) return HLBM_EHIP;
+      b->steps += (int64_t)len * every;
       pending = fused;  // a replayed cycle leaves a correction pending as an eager one does
     }
   }

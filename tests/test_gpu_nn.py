@@ -355,30 +355,35 @@ def test_fused_inference_equals_layer_kernels(B, H, W):
                               f"clip {clip} fused {fused} {B}x{H}x{W}")
 
 
-def test_closure_step_tiles_mixed_call_lengths():
-    """Tile kernels with the correction applied by the next cycle's first
-    step: calls of 2, 4, 1, 3 and 2 cycles (graphs captured with and without
-    a pending correction at their start, the last correction of each call
-    applied before it returns) equal the same calls run eagerly, bit for bit,
-    and the state after every call is the corrected one (a plain moments pass
-    of it equals the one of the eager run)."""
+@pytest.mark.parametrize("kernel", ["tiles", "strips"])
+def test_closure_step_mixed_call_lengths(kernel):
+    """Calls of 2, 4, 1, 3, 2, 11 and 9 cycles (two-cycle graphs and
+    eight-cycle ones, captured with and without a pending correction at
+    their start; with the tile kernels the correction is applied by the next
+    cycle's first step and the last one of each call before it returns)
+    equal the same calls run eagerly, bit for bit, and the state after every
+    call is the corrected one (a plain moments pass of it equals the one of
+    the eager run)."""
     params, flds = closure_batch(count=3, n=64, seed=40)
     net_params = rand_params(41)
     net_params[2] = (net_params[2][0] * 0.01, net_params[2][1] * 0.0)
     A = BatchSolver(params, flds)
     E = BatchSolver(params, flds)
     for S in (A, E):
-        S.set_tile(32, 16, kernel="tiles")
+        if kernel == "tiles":
+            S.set_tile(32, 16, kernel="tiles")
+        else:
+            S.set_tile(64, 8)
     na, ne = (make_net(3, 64, 64, net_params) for _ in range(2))
     for nt in (na, ne):
         nt.set_norm(np.array([1.0, 0, 0, 0.2], np.float32), np.array([0.03, 0.05, 0.05, 0.01], np.float32),
                     np.zeros(4, np.float32), np.array([1e-4, 1e-4, 1e-4, 1e-5], np.float32))
-    for rep, n in enumerate((2, 4, 1, 3, 2)):
+    for rep, n in enumerate((2, 4, 1, 3, 2, 11, 9)):
         A.closure_step(na, n, every=4, graph=True)
         E.closure_step(ne, n, every=4, graph=False)
         torch.cuda.synchronize()
         assert torch.equal(moments_cat(A), moments_cat(E)), rep
-    assert A.steps == E.steps == 4 * 12
+    assert A.steps == E.steps == 4 * 32
 
 
 def test_closure_step_one_step_tiles_equal_manual_sequence():
