@@ -130,7 +130,8 @@ int hlbm_batch_correct(hlbm_batch *b, const float *x, const float *delta, int32_
  * hlbm_batch_correct.  The network must have been created for max_batch >=
  * count and the domains' ny x nx, and trained for increments over `every`
  * steps; its workspace holds the moments and increments.  use_graph = 1
- * replays a captured two-cycle hipGraph (stream must not be NULL).  With
+ * replays captured hipGraphs of eight cycles while that many remain, then
+ * of two, and runs the rest eagerly (stream must not be NULL).  With
  * the HLBM_BATCH_TILES kernel (hlbm_batch_set_shape) the same results come
  * with fewer passes over the state: a cycle's last step also writes the
  * moments, and a cycle's correction is applied by the next cycle's first
