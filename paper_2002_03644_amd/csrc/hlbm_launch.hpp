@@ -57,20 +57,37 @@ inline TileShape step_tile(int nx, int ny, int tile_w, int tile_h, int elem_size
 
 // Tile shape of the two-step sweep (periodic domains).  Its workgroup reads a
 // radius-4 halo, rows + 8 rows for `rows` output rows, so it takes taller
-// strips than the one-step sweep: at 8192^2 FP32 (ms per step) 192 x 16
-// 1.023, x 32 0.911, x 48 0.891, x 64 0.888, x 96 0.906; 128 x 32 0.924,
-// x 64 0.892; 256 x 64 1.736 (two workgroups per CU in LDS).  Small grids
-// halve the strips down to 8 rows until about 384 workgroups exist (the
-// sweep holds three workgroups per CU at 192 columns in FP32).  FP64 keeps
-// 128-column tiles, whose two levels of rings fit the LDS of one workgroup.
+// strips than the one-step sweep.  FP32 grids from 1024 columns on take
+// 184-column tiles: tile plus halo fill three whole waves (192 columns leave
+// a fourth wave with 8 of 64 lanes busy) and, with the s and theta rings cut
+// to four rows, four workgroups fit a CU's LDS.  At 8192^2 (ms per step):
+// 184 x 64 0.784, x 96 0.791, x 48 0.794, x 32 0.790 against 192 x 64 0.832
+// (0.888 before the rings were cut).  Their strips are the tallest of 64,
+// 32, 16 and 8 rows that give at least 768 workgroups and fill the last
+// round of 1024 resident ones (four per CU on 256 CUs) at least three
+// quarters: best or within 2 % of best at 1024^2 (8 rows), 1500^2 (16),
+// 2048^2 (32), 3000^2 (64), 4096^2 (32), 6000^2 and 8192^2 (64), and
+// 3-35 % faster than 192-column tiles from 1024^2 on, except level at
+// 3000^2.  Narrower grids keep 128 columns (halving the strips down to 8
+// rows until about 384 workgroups exist); FP64 keeps 128-column tiles,
+// whose two levels of rings fit the LDS of one workgroup.
 inline TileShape step2_tile(int nx, int ny, int tile_w, int tile_h, int elem_size) {
   TileShape t;
-  t.bw = tile_w ? tile_w
-                : (nx <= 64 ? 64 : (nx >= 1024 && elem_size == 4 ? 192 : 128));
+  const bool wide = nx >= 1024 && elem_size == 4;
+  t.bw = tile_w ? tile_w : (nx <= 64 ? 64 : (wide ? 184 : 128));
   int rows = tile_h ? tile_h : 64;
   if (!tile_h) {
     const long long nbx = (nx + t.bw - 1) / t.bw;
-    while (rows > 8 && nbx * ((ny + rows - 1) / rows) < 384) rows /= 2;
+    if (t.bw == 184) {
+      constexpr long long kResident = 1024;
+      for (; rows > 8; rows /= 2) {
+        const long long nb = nbx * ((ny + rows - 1) / rows);
+        const long long rounds = (nb + kResident - 1) / kResident;
+        if (nb >= 768 && 4 * nb >= 3 * rounds * kResident) break;
+      }
+    } else {
+      while (rows > 8 && nbx * ((ny + rows - 1) / rows) < 384) rows /= 2;
+    }
   }
   if (rows > ny) rows = ny;
   t.rows = rows;

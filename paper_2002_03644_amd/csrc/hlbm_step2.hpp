@@ -39,11 +39,14 @@
 namespace hlbm {
 namespace HLBM_NS {
 
-// LDS rings of one time level (the depths of the one-step sweep's rings).
+// LDS rings of one time level (the depths of the one-step sweep's rings,
+// except s and theta: C reads them from LDS only along x, on its own row,
+// and takes the y-stencil from the lane's register window, so four rows
+// hold every row still to be read).
 template <int W>
 struct LevelRings {
   real ux[2][W], uy[2][W], gx[2][W];
-  real th[5][W], s[6][W];
+  real th[4][W], s[4][W];
   real f0[2][2][W];  // populations 1, 3   (c_y =  0)
   real fp[3][2][W];  // populations 5, 6   (c_y = +1)
   real fm[2][W];     // populations 7, 8   (c_y = -1)
@@ -69,7 +72,24 @@ struct LevelRegs {
   real nB_ux = 0, nB_uy = 0, nB_rho = 1, nB_th = 1, nB_phi = 0;
   real cB_ux = 0, cB_uy = 0, cB_rho = 1, cB_th = 1, cB_phi = 0;
   real nB_f0 = 0, nB_f2 = 0, nB_f4 = 0, cB_f0 = 0, cB_f2 = 0, cB_f2b = 0;
+  // the lane's own column of s and of the theta values C's Laplacian reads,
+  // over the last six (five) rows A wrote, oldest first: C(k) runs after
+  // A(k + 3) and reads rows k - 2 .. k + 2 (k - 1 .. k + 1)
+  real ws[6] = {0, 0, 0, 0, 0, 0};
+  real wt[5] = {0, 0, 0, 0, 0};
 };
+
+// Shifts one row into the register windows (level_a does it for the row it
+// writes; a lane whose A stage has run out pushes a placeholder, so the
+// windows stay aligned with C's rows).
+__device__ __forceinline__ void level_push(LevelRegs &g, const real sv, const real lap_val) {
+#pragma unroll
+  for (int q = 0; q < 5; ++q) g.ws[q] = g.ws[q + 1];
+  g.ws[5] = sv;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) g.wt[q] = g.wt[q + 1];
+  g.wt[4] = lap_val;
+}
 
 // A(j): moments of one node of row j from its nine populations and entropy.
 template <int W>
@@ -89,9 +109,10 @@ __device__ __forceinline__ void level_a(const DomainArgs &d, LevelRegs &g, Level
   }
   R.ux[j & 1][ri] = ux;
   R.uy[j & 1][ri] = uy;
-  R.th[j % 5][ri] = lap_val;
+  R.th[j & 3][ri] = lap_val;
   R.gx[j & 1][ri] = m.rho * ux * ((real(1) - th) - ux * ux);
-  R.s[j % 6][ri] = sv;
+  R.s[j & 3][ri] = sv;
+  level_push(g, sv, lap_val);
   g.m_ux = g.s0_ux;
   g.m_uy = g.s0_uy;
   g.m_gy = g.c_gy;
@@ -224,15 +245,13 @@ __device__ __forceinline__ void level_c(const DomainArgs &d, const LevelRegs &g,
   Fo[4] = g.nB_f4;
   Fo[7] = R.fm[0][ri + 1];
   Fo[8] = R.fm[1][ri - 1];
-  const int s0 = k % 6, s1 = (k + 1) % 6, s2 = (k + 2) % 6, sm1 = (k + 5) % 6,
-            sm2 = (k + 4) % 6;
-  const real sc = R.s[s0][ri];
+  const int s0 = k & 3;
+  const real sc = g.ws[2];
   const real advx = muscl_term(g.cB_ux, R.s[s0][ri - 2], R.s[s0][ri - 1], sc, R.s[s0][ri + 1],
                                R.s[s0][ri + 2]);
-  const real advy = muscl_term(g.cB_uy, R.s[sm2][ri], R.s[sm1][ri], sc, R.s[s1][ri], R.s[s2][ri]);
-  const int t0 = k % 5, tn = (k + 1) % 5, ts = (k + 4) % 5;
-  const real lap = ((R.th[t0][ri + 1] + R.th[t0][ri - 1]) + (R.th[tn][ri] + R.th[ts][ri])) -
-                   real(4) * R.th[t0][ri];
+  const real advy = muscl_term(g.cB_uy, g.ws[0], g.ws[1], sc, g.ws[3], g.ws[4]);
+  const real lap = ((R.th[s0][ri + 1] + R.th[s0][ri - 1]) + (g.wt[2] + g.wt[0])) -
+                   real(4) * g.wt[1];
   snew = sc - (advx + advy) + div_fast(d.lambda * lap + g.cB_phi, g.cB_rho * g.cB_th);
 }
 
@@ -311,11 +330,15 @@ __device__ __forceinline__ void sweep_tile2(const DomainArgs &d, const real *src
 #pragma unroll
       for (int q = 0; q < kQ; ++q) F[q] = ld[q];
       level_a(d, g1, R.L1, i + 1, ri, F, ld[9], bad);
+    } else if (a1) {
+      level_push(g1, real(0), real(0));
     }
     if (c1 && i >= 4 && i - 2 <= nrow + 5) {
       real Fo[kQ], snew;
       level_c(d, g1, R.L1, i - 2, ri, Fo, snew);
       level_a(d, g2, R.L2, i - 2, ri, Fo, snew, bad);
+    } else if (c1 && i >= 4) {
+      level_push(g2, real(0), real(0));
     }
     if (c2 && i >= 9) {
       const int k = i - 5;

@@ -89,7 +89,7 @@ def test_launch_plan_and_steps_per_launch():
     assert launch_plan(_params(bc_y="wall", wall_theta=0.2))[0] == 1
     assert launch_plan(_params(steps_per_launch=1))[0] == 1
     spl, tw, th = launch_plan(_params(nx=8192, ny=8192))
-    assert (tw, th) == (192, 64)
+    assert (tw, th) == (184, 64)
     assert launch_plan(_params(nx=100, ny=100, dtype="f64", steps_per_launch=2))[0] == 2
     for bad in (dict(steps_per_launch=3), dict(steps_per_launch=-1),
                 dict(steps_per_launch=2, bc_x="extrapolate"),
@@ -172,8 +172,14 @@ def test_default_launch_shape(nx, ny, dt, shape):
 
 
 @pytest.mark.parametrize("nx,ny,dt,shape", [
-    (8192, 8192, "f32", (192, 64)),   # the bench grid
-    (1024, 1024, "f32", (192, 16)),   # halved until about 384 workgroups
+    (8192, 8192, "f32", (184, 64)),   # the bench grid
+    (6000, 6000, "f32", (184, 64)),   # 3102 workgroups: four rounds of 1024, 76 % full
+    (4096, 4096, "f32", (184, 32)),   # 64 rows: 1472 workgroups fill two rounds to 72 %
+    (3000, 3000, "f32", (184, 64)),   # 799 workgroups
+    (2048, 2048, "f32", (184, 32)),   # halved until 768 workgroups
+    (1500, 1500, "f32", (184, 16)),
+    (1024, 1024, "f32", (184, 8)),
+    (1000, 1000, "f32", (128, 16)),   # narrower grids: 128 columns, about 384 workgroups
     (256, 256, "f32", (128, 8)),
     (64, 64, "f32", (64, 8)),
     (1, 1, "f32", (64, 1)),           # never more rows than ny
