@@ -76,7 +76,9 @@ typedef struct {
   int32_t e2_off;       /* 0: with the polyatomic E2 term (present model);
                            1: without it (original-model ablation) */
   int32_t tile_w;       /* tile width in columns (64, 128, 192 or 256; the workgroup has
-                           tile_w + 64 lanes, the extra wave holds the halo), 0 = auto */
+                           tile_w + 64 lanes, the extra wave holds the halo; 184 and 248
+                           too with steps_per_launch = 2, whose workgroup is tile_w + 8
+                           lanes rounded up to whole waves), 0 = auto */
   int32_t tile_h;       /* output rows per workgroup strip (>= 1), 0 = auto;
                            hlbm_launch_shape reports what a step will use */
   double gamma;         /* heat-capacity ratio, > 1 */
@@ -146,9 +148,11 @@ int hlbm_launch_shape(const hlbm_params *p, int32_t *host_tile_w, int32_t *host_
 
 /* Launch plan of hlbm_step for these parameters: steps per kernel launch (1
  * or 2, see steps_per_launch) and the tile shape of that launch (for two
- * steps per launch: tile_w / tile_h as given, or 192-column tiles from 1024
- * columns in FP32, 128 otherwise, 64 for nx <= 64, with 64-row strips halved
- * down to 8 rows until about 384 workgroups exist).  HLBM_OK, or
+ * steps per launch: tile_w / tile_h as given, or 184-column tiles from 1024
+ * columns in FP32, with the tallest strips of 64, 32, 16 or 8 rows that give
+ * at least 768 workgroups and fill the last round of 1024 resident ones at
+ * least three quarters; 128 columns otherwise, 64 for nx <= 64, with 64-row
+ * strips halved down to 8 rows until about 384 workgroups exist).  HLBM_OK, or
  * HLBM_EINVAL if the parameters are invalid or a pointer is NULL.
  * Host-only. */
 int hlbm_launch_plan(const hlbm_params *p, int32_t *host_steps_per_launch, int32_t *host_tile_w,
@@ -300,8 +304,8 @@ int hlbm_batch_moments(hlbm_batch *b, void *rho, void *ux, void *uy, void *s, vo
 int hlbm_batch_status(hlbm_batch *b, int32_t *host_flags, hlbm_stream_t stream);
 
 /* Kernel and tile shape of the batched step.  HLBM_BATCH_STRIPS: tile_w in
- * {64, 128, 192, 256} (64, 128 or 192 for two steps per launch, 64 or 128
- * then in FP64), tile_h >= 4.  HLBM_BATCH_TILES: (tile_w, tile_h) in
+ * {64, 128, 192, 256} (64, 128, 184 or 192 for two steps per launch, 64 or
+ * 128 then in FP64), tile_h >= 4.  HLBM_BATCH_TILES: (tile_w, tile_h) in
  * {(32, 8), (32, 16), (64, 8), (32, 32), (64, 16)}, the first three in FP64.
  * HLBM_EINVAL for any other shape.  Drops the captured graphs.  Synchronises
  * `stream`. */
@@ -313,7 +317,7 @@ int hlbm_batch_set_tile(hlbm_batch *b, int32_t tile_w, int32_t tile_h, hlbm_stre
 
 /* Time `steps` steps (after one untimed launch; rounded up to even when the
  * strip kernel takes two steps per launch) for every shape that
- * hlbm_batch_set_shape accepts among strips {64, 128, 192, 256} x {4, 8, 16,
+ * hlbm_batch_set_shape accepts among strips {64, 128, 184, 192, 256} x {4, 8, 16,
  * 32, 64, 128} and all tile shapes, twice each, keep the fastest and report
  * its kernel and shape (outputs may be NULL).  scratch: a device buffer of hlbm_batch_state_bytes(b) bytes
  * owned by the caller; the state at entry is saved there and loaded again
