@@ -82,11 +82,12 @@ def patch_check(S, params, samples, steps_before, tol_F, tol_s, bc_x="periodic",
 @pytest.mark.parametrize("steps", [2, 1])
 def test_f32_turbulence_8192_sampled(steps):
     """Decaying turbulence 8192^2, FP32, default plan (as bench.py: two steps
-    per launch on 192 x 64 tiles, the last tile column ragged at x = 8064;
+    per launch on 184 x 64 tiles, the last tile column ragged at x = 8096;
     one step: the one-step kernel on 192 x 16 tiles): after 20 steps, one
-    more launch matches the oracle's steps of the same FP32 state on 96
-    patches -- random nodes plus tile seams (x = 191, 192, 8063, 8064), strip
-    seams (y = 15, 16, 63, 64), the 128 x 32 seams and the periodic corners.
+    more launch matches the oracle's steps of the same FP32 state on 105
+    patches -- random nodes plus tile seams (x = 183, 184, 8095, 8096 and
+    191, 192, 8063, 8064), strip seams (y = 15, 16, 63, 64), the 128 x 32
+    seams and the periodic corners.
     FP32 arithmetic: 1e-6 on F (values ~0.01-0.4), 2e-6 on s (|s| ~ 1.3) per
     step."""
     n = 8192
@@ -105,7 +106,10 @@ def test_f32_turbulence_8192_sampled(steps):
                 (15, 191), (16, 192), (15, 192), (16, 191), (16 * 300 + 15, 8063),
                 (16 * 300 + 16, 8064), (8191, 8064), (16 * 511 + 15, 192 * 41 + 191),
                 (63, 191), (64, 192), (63, 192), (64, 191), (64 * 70 + 63, 8063),
-                (64 * 70 + 64, 8064), (64 * 127 + 63, 192 * 41 + 191), (8191, 191)]
+                (64 * 70 + 64, 8064), (64 * 127 + 63, 192 * 41 + 191), (8191, 191),
+                (63, 183), (64, 184), (63, 184), (64, 183), (64 * 70 + 63, 8095),
+                (64 * 70 + 64, 8096), (8191, 8096), (64 * 127 + 63, 184 * 41 + 183),
+                (16 * 300 + 15, 184 * 20 + 183)]
     patch_check(S, params, samples, 20, tol_F=1e-6 * steps, tol_s=2e-6 * steps, steps=steps)
 
 
