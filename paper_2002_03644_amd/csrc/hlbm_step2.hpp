@@ -26,7 +26,10 @@
 // Iteration i issues the loads of row i + 1, runs B1(i - 1) and B2(i - 4),
 // a barrier, A1(i + 1), C1(i - 2) -> A2(i - 2), C2(i - 5), a barrier.  Each
 // level keeps the one-step sweep's distances between A, B and C, so its
-// rings have the same depths.
+// rings have the same depths, except those of s and theta (see LevelRings):
+// C takes their y-stencil from per-lane registers, which leaves 26 rows of
+// CW + 8 per level in LDS, so four workgroups of 184-column tiles (three
+// whole waves each) fit a compute unit.
 //
 // Boundaries: out-of-range columns and rows wrap.  A halo lane then computes
 // level n + 1 of the wrapped node from the wrapped stencil, bit for bit what
