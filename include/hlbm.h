@@ -76,7 +76,7 @@ typedef struct {
   int32_t e2_off;       /* 0: with the polyatomic E2 term (present model);
                            1: without it (original-model ablation) */
   int32_t tile_w;       /* tile width in columns (64, 128, 192 or 256; the workgroup has
-                           tile_w + 64 lanes, the extra wave holds the halo; 184 and 248
+                           tile_w + 64 lanes, the extra wave holds the halo; 120, 184, 248
                            too with steps_per_launch = 2, whose workgroup is tile_w + 8
                            lanes rounded up to whole waves), 0 = auto */
   int32_t tile_h;       /* output rows per workgroup strip (>= 1), 0 = auto;
@@ -151,8 +151,10 @@ int hlbm_launch_shape(const hlbm_params *p, int32_t *host_tile_w, int32_t *host_
  * steps per launch: tile_w / tile_h as given, or 184-column tiles from 1024
  * columns in FP32, with the tallest strips of 64, 32, 16 or 8 rows that give
  * at least 768 workgroups and fill the last round of 1024 resident ones at
- * least three quarters; 128 columns otherwise, 64 for nx <= 64, with 64-row
- * strips halved down to 8 rows until about 384 workgroups exist).  HLBM_OK, or
+ * least three quarters; 120 columns from 640 columns in FP32, halved down to
+ * 8 rows until 768 workgroups exist; 128 columns otherwise, 64 for nx <= 64,
+ * with 64-row strips halved down to 8 rows until about 384 workgroups
+ * exist).  HLBM_OK, or
  * HLBM_EINVAL if the parameters are invalid or a pointer is NULL.
  * Host-only. */
 int hlbm_launch_plan(const hlbm_params *p, int32_t *host_steps_per_launch, int32_t *host_tile_w,

@@ -203,9 +203,9 @@ int hlbm_validate(const hlbm_params *p) {
     return HLBM_EINVAL;
   if (p->tile_w != 0 && p->tile_w != 64 && p->tile_w != 128 && p->tile_w != 192 &&
       p->tile_w != 256 &&
-      !((p->tile_w == 184 || p->tile_w == 248) && p->steps_per_launch == 2 &&
-        p->dtype == HLBM_F32))
-    return HLBM_EINVAL;  // 184 and 248: the two-step sweep's whole-wave widths
+      !((p->tile_w == 120 || p->tile_w == 184 || p->tile_w == 248) &&
+        p->steps_per_launch == 2 && p->dtype == HLBM_F32))
+    return HLBM_EINVAL;  // 120, 184 and 248: the two-step sweep's whole-wave widths
   if (p->tile_h < 0) return HLBM_EINVAL;
   if (!(isfinite(p->gamma) && p->gamma > 1.0)) return HLBM_EINVAL;
   if (!finite_pos(p->prandtl)) return HLBM_EINVAL;

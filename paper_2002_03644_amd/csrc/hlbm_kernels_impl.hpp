@@ -91,6 +91,7 @@ hipError_t step2(const HostDomain &h, const void *src, void *dst, unsigned *stat
   if (sizeof(real) == 4) {
     switch (tile.bw) {
       HLBM_STEP2_CASE(64)
+      HLBM_STEP2_CASE(120)
       HLBM_STEP2_CASE(128)
       HLBM_STEP2_CASE(184)
       HLBM_STEP2_CASE(192)

@@ -68,17 +68,25 @@ inline TileShape step_tile(int nx, int ny, int tile_w, int tile_h, int elem_size
 // quarters: best or within 2 % of best at 1024^2 (8 rows), 1500^2 (16),
 // 2048^2 (32), 3000^2 (64), 4096^2 (32), 6000^2 and 8192^2 (64), and
 // 3-35 % faster than 192-column tiles from 1024^2 on, except level at
-// 3000^2.  Narrower grids keep 128 columns (halving the strips down to 8
-// rows until about 384 workgroups exist); FP64 keeps 128-column tiles,
-// whose two levels of rings fit the LDS of one workgroup.
+// 3000^2.  FP32 grids of 640 to 1023 columns take 120-column tiles (two
+// whole waves, six workgroups per CU) with strips halved down to 8 rows
+// until 768 workgroups exist: 8 rows at 768^2 and 1000^2, 29.3 and 41.3 k
+// MLUPS against 25.0 and 30.9 k on 128-column tiles (at 512^2 the 128
+// columns stay ahead, 13.8 against 13.1 k).  Narrower grids keep 128
+// columns (halving the strips down to 8 rows until about 384 workgroups
+// exist); FP64 keeps 128-column tiles, whose two levels of rings fit the
+// LDS of one workgroup.
 inline TileShape step2_tile(int nx, int ny, int tile_w, int tile_h, int elem_size) {
   TileShape t;
   const bool wide = nx >= 1024 && elem_size == 4;
-  t.bw = tile_w ? tile_w : (nx <= 64 ? 64 : (wide ? 184 : 128));
+  const bool mid = nx >= 640 && elem_size == 4;
+  t.bw = tile_w ? tile_w : (nx <= 64 ? 64 : (wide ? 184 : (mid ? 120 : 128)));
   int rows = tile_h ? tile_h : 64;
   if (!tile_h) {
     const long long nbx = (nx + t.bw - 1) / t.bw;
-    if (t.bw == 184) {
+    if (t.bw == 120) {
+      while (rows > 8 && nbx * ((ny + rows - 1) / rows) < 768) rows /= 2;
+    } else if (t.bw == 184) {
       constexpr long long kResident = 1024;
       for (; rows > 8; rows /= 2) {
         const long long nb = nbx * ((ny + rows - 1) / rows);

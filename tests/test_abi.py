@@ -179,7 +179,9 @@ def test_default_launch_shape(nx, ny, dt, shape):
     (2048, 2048, "f32", (184, 32)),   # halved until 768 workgroups
     (1500, 1500, "f32", (184, 16)),
     (1024, 1024, "f32", (184, 8)),
-    (1000, 1000, "f32", (128, 16)),   # narrower grids: 128 columns, about 384 workgroups
+    (1000, 1000, "f32", (120, 8)),    # 640 .. 1023 columns: 120, halved until 768 workgroups
+    (768, 768, "f32", (120, 8)),
+    (600, 600, "f32", (128, 8)),      # narrower grids: 128 columns, about 384 workgroups
     (256, 256, "f32", (128, 8)),
     (64, 64, "f32", (64, 8)),
     (1, 1, "f32", (64, 1)),           # never more rows than ny
