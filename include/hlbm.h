@@ -107,7 +107,9 @@ typedef struct {
                            (Sec. 2.3, Table 1); with e1_centred = e2_off = 1
                            this is that model */
   int32_t steps_per_launch; /* 0: automatic (2 for FP32 domains periodic along both
-                           axes, else 1); 1: one step per kernel launch; 2: two
+                           axes with at least 900,000 nodes, else 1; batch
+                           domains: 2 for every size, see hlbm_batch_step);
+                           1: one step per kernel launch; 2: two
                            steps per launch, reading the state once and writing
                            it once every two steps (periodic along both axes
                            only, HLBM_EINVAL otherwise).  The per-node
@@ -287,9 +289,10 @@ int hlbm_batch_init(hlbm_batch **out, const hlbm_params *params, int32_t count, 
                     size_t ws_bytes, const void *rho, const void *ux, const void *uy,
                     const void *s, hlbm_stream_t stream);
 
-/* Enqueue nsteps steps of all domains.  When every domain's own plan is two
- * steps per launch (FP32, periodic along both axes; see steps_per_launch)
- * the batch kernel advances two steps per launch, else one.  use_graph = 1
+/* Enqueue nsteps steps of all domains.  When every domain takes two steps
+ * per launch (FP32, periodic along both axes, steps_per_launch 0 or 2; the
+ * size rule of single domains does not apply) the batch kernel advances two
+ * steps per launch, else one.  use_graph = 1
  * (stream must not be NULL) replays a captured graph of sixteen launches
  * while enough steps remain, then one of two launches, and runs the rest
  * eagerly (an odd last step with a one-step launch); each graph is captured

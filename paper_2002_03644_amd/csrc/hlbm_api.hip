@@ -90,12 +90,26 @@ void rest_equilibrium(double rho, double theta, int order, double f[9]) {
   f[5] = f[6] = f[7] = f[8] = bd / 36.0;
 }
 
-// Steps per launch: two-step sweeps need periodic axes (validated), and are
-// the default for FP32 there; FP64's two-level sweep holds one wave per SIMD.
-int steps_per_launch(const hlbm_params *p) {
+// Steps per launch of a batch domain: two-step sweeps need periodic axes
+// (validated), and are the batch's choice for FP32 there (its two-step
+// tiles serve small domains); FP64's two-level sweep holds one wave per SIMD.
+int batch_steps_per_launch(const hlbm_params *p) {
   if (p->steps_per_launch) return p->steps_per_launch;
   const bool periodic = p->bc_x == HLBM_BC_PERIODIC && p->bc_y == HLBM_BC_PERIODIC;
   return periodic && p->dtype == HLBM_F32 ? 2 : 1;
+}
+
+// Steps per launch of a single domain: as for a batch domain, from
+// kTwoStepMinNodes nodes on.  Smaller grids give the two-step sweep too few
+// workgroups to fill the chip with its taller strips, and the one-step sweep
+// is faster there (MLUPS, one against two steps per launch: 512^2 17.8 k /
+// 13.5 k, 640^2 23.9 / 19.7, 768^2 28.0 / 27.7; 1000^2 35.8 / 38.4, 1024^2
+// 37.3 / 39.9).
+constexpr long long kTwoStepMinNodes = 900000;
+int steps_per_launch(const hlbm_params *p) {
+  if (p->steps_per_launch) return p->steps_per_launch;
+  const int spl = batch_steps_per_launch(p);
+  return spl == 2 && (long long)p->nx * p->ny < kTwoStepMinNodes ? 1 : spl;
 }
 
 hlbm::TileShape default_tile(const hlbm_params *p) {
@@ -818,7 +832,7 @@ int hlbm_batch_init(hlbm_batch **out, const hlbm_params *params, int32_t count, 
   b->ws = (char *)workspace;
   b->spl_strips = 2;  // two steps per launch when every domain would take them alone
   for (int k = 0; k < count; ++k)
-    if (steps_per_launch(&b->params[k]) != 2) b->spl_strips = 1;
+    if (batch_steps_per_launch(&b->params[k]) != 2) b->spl_strips = 1;
   b->spl = b->spl_strips;
   b->doms.resize(count);
   for (int k = 0; k < count; ++k) {

@@ -84,6 +84,9 @@ def test_validate_feq_order(order, ok):
 def test_launch_plan_and_steps_per_launch():
     from paper_2002_03644_amd import HLBM_EINVAL, launch_plan, validate
     assert launch_plan(_params(nx=8192, ny=8192))[0] == 2               # FP32 periodic
+    assert launch_plan(_params(nx=1000, ny=1000))[0] == 2               # from 900,000 nodes
+    assert launch_plan(_params(nx=768, ny=768))[0] == 1                 # smaller: one step
+    assert launch_plan(_params(nx=4096, ny=256))[0] == 2                # nodes, not width
     assert launch_plan(_params(nx=8192, ny=8192, dtype="f64"))[0] == 1  # FP64 default
     assert launch_plan(_params(bc_x="extrapolate"))[0] == 1
     assert launch_plan(_params(bc_y="wall", wall_theta=0.2))[0] == 1
