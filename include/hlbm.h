@@ -309,8 +309,8 @@ int hlbm_batch_moments(hlbm_batch *b, void *rho, void *ux, void *uy, void *s, vo
 int hlbm_batch_status(hlbm_batch *b, int32_t *host_flags, hlbm_stream_t stream);
 
 /* Kernel and tile shape of the batched step.  HLBM_BATCH_STRIPS: tile_w in
- * {64, 128, 192, 256} (64, 128, 184 or 192 for two steps per launch, 64 or
- * 128 then in FP64), tile_h >= 4.  HLBM_BATCH_TILES: (tile_w, tile_h) in
+ * {64, 128, 192, 256} (64, 120, 128, 184 or 192 for two steps per launch,
+ * 64 or 128 then in FP64), tile_h >= 4.  HLBM_BATCH_TILES: (tile_w, tile_h) in
  * {(32, 8), (32, 16), (64, 8), (32, 32), (64, 16)}, the first three in FP64.
  * HLBM_EINVAL for any other shape.  Drops the captured graphs.  Synchronises
  * `stream`. */
@@ -322,7 +322,7 @@ int hlbm_batch_set_tile(hlbm_batch *b, int32_t tile_w, int32_t tile_h, hlbm_stre
 
 /* Time `steps` steps (after one untimed launch; rounded up to even when the
  * strip kernel takes two steps per launch) for every shape that
- * hlbm_batch_set_shape accepts among strips {64, 128, 184, 192, 256} x {4, 8, 16,
+ * hlbm_batch_set_shape accepts among strips {64, 120, 128, 184, 192, 256} x {4, 8, 16,
  * 32, 64, 128} and all tile shapes, twice each, keep the fastest and report
  * its kernel and shape (outputs may be NULL).  scratch: a device buffer of hlbm_batch_state_bytes(b) bytes
  * owned by the caller; the state at entry is saved there and loaded again

@@ -535,9 +535,9 @@ struct hlbm_batch {
 
 namespace {
 
-// strip widths; 184 (tile plus halo in three whole waves) for two-step
-// strips only, FP32
-constexpr int kBatchTileW[5] = {64, 128, 184, 192, 256};
+// strip widths; 120 and 184 (tile plus halo in two and three whole waves)
+// for two-step strips only, FP32
+constexpr int kBatchTileW[6] = {64, 120, 128, 184, 192, 256};
 constexpr int kBatchMinRows = 4;  // short strips: small domains are bound by the serial sweep
 // Batches whose two state buffers fit in this many bytes (the 256 MiB
 // last-level cache) walk their items XCD by XCD, which keeps neighbouring
@@ -623,8 +623,8 @@ bool batch_shape_ok(const hlbm_batch *b, int kind, int tw, int th) {
     return b->dtype == HLBM_F64 ? hlbm::f64::tile_shape_supported(tw, th)
                                 : hlbm::f32::tile_shape_supported(tw, th);
   if (kind != HLBM_BATCH_STRIPS) return false;
-  if (tw != 64 && tw != 128 && tw != 184 && tw != 192 && tw != 256) return false;
-  if (tw == 184 && (b->spl_strips != 2 || b->dtype == HLBM_F64)) return false;
+  if (tw != 64 && tw != 120 && tw != 128 && tw != 184 && tw != 192 && tw != 256) return false;
+  if ((tw == 120 || tw == 184) && (b->spl_strips != 2 || b->dtype == HLBM_F64)) return false;
   if (b->spl_strips == 2 && (tw == 256 || (b->dtype == HLBM_F64 && tw == 192)))
     return false;  // the two-step strip kernel's widths
   return th >= kBatchMinRows;
@@ -954,7 +954,7 @@ int hlbm_batch_autotune(hlbm_batch *b, int32_t steps, void *scratch, int32_t *ho
                         int32_t *host_best_w, int32_t *host_best_h, hlbm_stream_t stream) {
   if (!b || steps < 1 || !scratch) return HLBM_EINVAL;
   hipStream_t st = (hipStream_t)stream;
-  // candidate shapes: strips {64, 128, 184, 192, 256} x {4, ..., 128}, then tiles
+  // candidate shapes: strips {64, 120, 128, 184, 192, 256} x {4, ..., 128}, then tiles
   struct Shape {
     int kind, w, h;
   };

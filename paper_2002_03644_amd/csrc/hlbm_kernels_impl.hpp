@@ -215,7 +215,11 @@ hipError_t step_batch(const void *doms, const long long *offs, const void *items
   case 128:
     hipLaunchKernelGGL(k_step_batch<128>, dim3(grid), dim3(128 + 64), 0, st, a);
     break;
-  case 184:  // odd last steps of batches on 184-column two-step strips (FP32)
+  case 120:  // odd last steps of batches on 120- and 184-column two-step strips (FP32)
+    if (sizeof(real) != 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_step_batch<120>, dim3(grid), dim3(120 + 64), 0, st, a);
+    break;
+  case 184:
     if (sizeof(real) != 4) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_step_batch<184>, dim3(grid), dim3(184 + 64), 0, st, a);
     break;
@@ -257,6 +261,7 @@ hipError_t step_batch2(const void *doms, const long long *offs, const void *item
   if (sizeof(real) == 4) {
     switch (cw) {
       HLBM_BATCH2_CASE(64)
+      HLBM_BATCH2_CASE(120)
       HLBM_BATCH2_CASE(128)
       HLBM_BATCH2_CASE(184)
       HLBM_BATCH2_CASE(192)
@@ -282,6 +287,9 @@ int batch2_blocks_per_cu(int cw) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch2<64>, step2_threads(64), 0);
   if (cw == 128)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch2<128>, step2_threads(128),
+                                                     0);
+  if (cw == 120 && sizeof(real) == 4)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch2<120>, step2_threads(120),
                                                      0);
   if (cw == 184 && sizeof(real) == 4)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch2<184>, step2_threads(184),
@@ -487,6 +495,8 @@ int batch_blocks_per_cu(int cw) {
   hipError_t e = hipErrorInvalidValue;
   if (cw == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch<64>, 128, 0);
   if (cw == 128) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch<128>, 192, 0);
+  if (cw == 120 && sizeof(real) == 4)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch<120>, 184, 0);
   if (cw == 184 && sizeof(real) == 4)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch<184>, 248, 0);
   if (cw == 192) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_batch<192>, 256, 0);

@@ -72,14 +72,14 @@ def test_batch_bitwise_equals_single_domains(dtype, graph, tile):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("graph,tile,steps", [(False, (128, 32), 23), (True, (128, 16), 37),
                                               (True, (64, 8), 23), (True, (184, 16), 23),
-                                              (False, (184, 8), 9)])
+                                              (False, (184, 8), 9), (True, (120, 8), 23)])
 def test_two_step_batch_bitwise_equals_single_domains(dtype, graph, tile, steps):
     """All domains periodic, two steps per launch (an odd count ends with a
-    one-step launch, on 184-column strips the one-step kernel of that width):
-    each domain equals its single run with the same tile and plan, bit for
-    bit.  184-column strips are FP32 only."""
-    if dtype == "f64" and tile[0] == 184:
-        pytest.skip("184-column strips take FP32 domains only")
+    one-step launch, on 120- and 184-column strips the one-step kernel of
+    that width): each domain equals its single run with the same tile and
+    plan, bit for bit.  Those two widths are FP32 only."""
+    if dtype == "f64" and tile[0] in (120, 184):
+        pytest.skip("120- and 184-column strips take FP32 domains only")
     params, fields = domain_set(dtype, spl=2, periodic=True)
     B = BatchSolver(params, fields)
     B.set_tile(*tile)
@@ -190,7 +190,7 @@ def test_autotune_restores_state_and_caches(tmp_path):
     cache = str(tmp_path / "tune.json")
     kern, w, h = B.autotune(steps=2, cache_path=cache)
     if kern == "strips":
-        assert w in (64, 128, 184, 192, 256) and h in (4, 8, 16, 32, 64, 128)
+        assert w in (64, 120, 128, 184, 192, 256) and h in (4, 8, 16, 32, 64, 128)
     else:
         assert kern == "tiles" and (w, h) in ((32, 8), (32, 16), (64, 8), (32, 32), (64, 16))
     assert B.plan()[1:] == (kern, w, h)
