@@ -323,3 +323,26 @@ def test_network_binding_checks_field_extents_and_idx():
         _check_idx(torch.zeros(4, dtype=torch.int32), 5, "cpu")    # too few entries
     with pytest.raises(ValueError):
         _check_idx(torch.zeros(5, dtype=torch.int64), 5, "cpu")    # wrong dtype
+
+
+def test_default_plans_are_built_shapes():
+    """Over grids from 1 x 1 to 15446^2 (periodic and extrapolated, FP32 and
+    FP64), the default plan names a tile width the kernels are built for
+    with that plan and a strip height of at least 1 and at most ny."""
+    from paper_2002_03644_amd import launch_plan
+    sizes = [1, 2, 5, 31, 64, 65, 100, 200, 511, 512, 640, 700, 767, 768, 1000, 1023, 1024,
+             1031, 1500, 2048, 3000, 4096, 6000, 8192, 12288, 15446]
+    for dt in ("f32", "f64"):
+        for bc in ("periodic", "extrapolate"):
+            for nx in sizes:
+                for ny in (1, 3, 64, 300, nx):
+                    if 9 * nx * ny >= 2 ** 31:
+                        continue
+                    spl, tw, th = launch_plan(_params(nx=nx, ny=ny, dtype=dt, bc_x=bc))
+                    if spl == 2:
+                        built = (64, 120, 128, 184) if dt == "f32" else (64, 128)
+                    else:
+                        built = (64, 128, 192, 256)
+                    assert tw in built, (dt, bc, nx, ny, spl, tw)
+                    assert 1 <= th <= ny, (dt, bc, nx, ny, spl, th)
+                    assert spl == 1 or (bc == "periodic" and dt == "f32"), (dt, bc, nx, ny)
