@@ -683,8 +683,8 @@ hipError_t batch_launch(hlbm_batch *b, int from, hipStream_t st);
 
 // Ping-pong step pairs per long graph.  Replaying a two-step graph leaves a
 // gap of a few microseconds between replays, which for small batches (8 x
-// 256^2: 23 us per step) costs about 8 %; sixteen steps per replay recover
-// it (21.2 us).
+// 256^2, then on strips: 23 us per step) cost about 8 %; sixteen steps per
+// replay recovered it (21.2 us).
 constexpr int kLongPairs = 8;
 // Corrected cycles per long closure graph (see hlbm_closure_step).
 constexpr int kLongCycles = 8;

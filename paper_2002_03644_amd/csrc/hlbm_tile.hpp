@@ -30,7 +30,8 @@
 // and runs the stages again on the TW x TH tile: one load and one store of
 // the state per two steps.  It runs 512 threads per workgroup: with 256 each
 // thread holds twice the slots and 173 registers, two waves per SIMD, and
-// 8 x 256^2 steps take 16.2 against 14.0 us.
+// 8 x 256^2 steps took 16.2 against 14.0 us (before the batch kernels'
+// XCD-contiguous walk, which brought the 512-thread kernel to 13 us).
 #pragma once
 
 namespace hlbm {
